@@ -1,0 +1,79 @@
+"""Seeded material models, evaluated per element at the element centroid.
+
+Layered model on [0, 10]^3 with depth measured from the top face z = 10:
+layer index Lz = min(3, floor((10 - z) / 2.5)), so the interfaces sit at
+z = 7.5, 5 and 2.5 and align with meshes of 16 and 24 cells per side.
+
+* P-wave speed of the layer: 1.5 + 2.5 * Lz / 3  (1.5, 2.333, 3.167, 4.0).
+* 5 % noise: a 48^3 standard-normal field (seed 2205, indexed [iz, iy, ix],
+  samples at cell centres of a 48^3 grid on [0, 10]^3) smoothed by a separable
+  Gaussian of width 0.5 length units (truncated at 4 widths, reflecting
+  edges), divided by its largest magnitude and sampled trilinearly:
+  cp = cp_layer * (1 + 0.05 * noise).
+* cs = cp / sqrt(3); rho = 1 + 2 * Lz / 3 (1.0 ... 3.0, no noise).
+* Lame parameters: mu = rho * cs^2, lambda = rho * cp^2 - 2 * mu.
+"""
+
+import numpy as np
+from scipy import ndimage
+
+MEDIUM_SEED = 2205
+NOISE_GRID = 48
+NOISE_SIGMA = 0.5
+NOISE_AMPLITUDE = 0.05
+BOX = 10.0
+
+
+def lame_from_velocities(cp, cs, rho):
+    """(rho, lambda, mu) from wave speeds and density."""
+    cp = np.asarray(cp, dtype=np.float64)
+    cs = np.asarray(cs, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    mu = rho * cs * cs
+    lam = rho * cp * cp - 2.0 * mu
+    return rho, lam, mu
+
+
+def homogeneous_medium(K, rho=1.0, cp=np.sqrt(3.0), cs=1.0):
+    """Constant material on K elements; default rho = 1, lambda = mu = 1."""
+    return lame_from_velocities(np.full(K, cp), np.full(K, cs),
+                                np.full(K, rho))
+
+
+def _layer(z):
+    return np.minimum(3, np.floor((BOX - z) / 2.5)).astype(np.float64)
+
+
+def _noise(points):
+    rng = np.random.default_rng(MEDIUM_SEED)
+    g = rng.standard_normal((NOISE_GRID, NOISE_GRID, NOISE_GRID))
+    hcell = BOX / NOISE_GRID
+    sm = ndimage.gaussian_filter(g, sigma=NOISE_SIGMA / hcell, mode="reflect",
+                                 truncate=4.0)
+    sm /= np.max(np.abs(sm))
+    # grid index of a point: x / hcell - 0.5 (samples at cell centres)
+    coords = np.stack([points[:, 2], points[:, 1], points[:, 0]]) / hcell - 0.5
+    return ndimage.map_coordinates(sm, coords, order=1, mode="nearest")
+
+
+def layered_medium(centroids):
+    """Returns (rho, lam, mu, cp) at the given [K, 3] centroids."""
+    z = centroids[:, 2]
+    Lz = _layer(z)
+    cp_layer = 1.5 + 2.5 * Lz / 3.0
+    cp = cp_layer * (1.0 + NOISE_AMPLITUDE * _noise(centroids))
+    cs = cp / np.sqrt(3.0)
+    rho = 1.0 + 2.0 * Lz / 3.0
+    r, lam, mu = lame_from_velocities(cp, cs, rho)
+    return r, lam, mu, cp
+
+
+def blob_start_medium(centroids, centre=(5.0, 5.0, 8.5), width=1.0,
+                      depth=0.10):
+    """Starting model for the gradient test: the layered model with cp lowered
+    by a Gaussian blob (10 % at its centre), cs = cp / sqrt(3), rho unchanged."""
+    rho, _, _, cp = layered_medium(centroids)
+    d2 = np.sum((centroids - np.asarray(centre)) ** 2, axis=1)
+    cp = cp * (1.0 - depth * np.exp(-d2 / (2.0 * width * width)))
+    r, lam, mu = lame_from_velocities(cp, cp / np.sqrt(3.0), rho)
+    return r, lam, mu, cp

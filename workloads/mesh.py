@@ -1,0 +1,118 @@
+"""Structured tetrahedral meshes of a cube (Kuhn / Freudenthal split).
+
+The cube [0, L]^3 is cut into n^3 cells; cell (i, j, k) has index
+c = i + n*(j + n*k).  Every cell is split into 6 tetrahedra, one per
+permutation p of the axes (taken in the order xyz, xzy, yxz, yzx, zxy, zyx):
+v0 is the cell's lower corner, v1 = v0 + h*e_p1, v2 = v1 + h*e_p2,
+v3 = v2 + h*e_p3.  When the vertex order gives a negative volume, v2 and v3
+are swapped so every tetrahedron is positively oriented.  Tetrahedron id is
+6*c + p.  The split is translation invariant, so it is conforming across cells
+and across periodic boundaries.
+
+Local face f of a tetrahedron is the face opposite local vertex f; this is the
+face numbering of the C ABI.
+"""
+
+import numpy as np
+
+_PERMS = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+
+BC_NONE = 0
+BC_FREE_SURFACE = 1
+BC_ABSORBING = 2
+
+
+def kuhn_cube(n, L=1.0, periodic=False, top_free_surface=True):
+    """Return a dict describing the Kuhn-split cube mesh.
+
+    Keys: ``vxyz`` float64 [nvert, 3]; ``etov`` int32 [K, 4];
+    ``vertex_periodic_id`` int32 [nvert] or None; ``face_bc`` int8 [K, 4]
+    (only read where a face has no neighbour: 1 = free surface, 2 =
+    absorbing); ``n``, ``L``, ``h``.
+
+    Boundary tags: faces lying on z = L are free surface when
+    ``top_free_surface`` is set, every other boundary face is absorbing.
+    Periodic meshes tag nothing (every face has a neighbour).
+    """
+    n = int(n)
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    h = L / n
+    m = n + 1
+    ii, jj, kk = np.meshgrid(np.arange(m), np.arange(m), np.arange(m),
+                             indexing="ij")
+    # vertex index v = i + m*(j + m*k)
+    vid = lambda i, j, k: i + m * (j + m * k)
+    nvert = m ** 3
+    vxyz = np.empty((nvert, 3), dtype=np.float64)
+    idx = vid(ii, jj, kk).ravel()
+    vxyz[idx, 0] = ii.ravel() * h
+    vxyz[idx, 1] = jj.ravel() * h
+    vxyz[idx, 2] = kk.ravel() * h
+
+    K = 6 * n ** 3
+    etov = np.empty((K, 4), dtype=np.int64)
+    c = 0
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                cell = i + n * (j + n * k)
+                for p, perm in enumerate(_PERMS):
+                    pos = np.array([i, j, k])
+                    verts = [vid(*pos)]
+                    for ax in perm:
+                        pos = pos.copy()
+                        pos[ax] += 1
+                        verts.append(vid(*pos))
+                    etov[6 * cell + p] = verts
+                    c += 1
+    # orientation fix: swap v2, v3 where the signed volume is negative
+    a = vxyz[etov[:, 1]] - vxyz[etov[:, 0]]
+    b = vxyz[etov[:, 2]] - vxyz[etov[:, 0]]
+    d = vxyz[etov[:, 3]] - vxyz[etov[:, 0]]
+    det = np.einsum("ki,ki->k", a, np.cross(b, d))
+    neg = det < 0
+    etov[neg, 2], etov[neg, 3] = etov[neg, 3].copy(), etov[neg, 2].copy()
+    etov = etov.astype(np.int32)
+
+    pid = None
+    face_bc = np.zeros((K, 4), dtype=np.int8)
+    if periodic:
+        pid = (np.mod(ii, n) + n * (np.mod(jj, n) + n * np.mod(kk, n)))
+        tmp = np.empty(nvert, dtype=np.int32)
+        tmp[idx] = pid.ravel()
+        pid = tmp
+    else:
+        for f in range(4):
+            others = [a_ for a_ in range(4) if a_ != f]
+            fv = vxyz[etov[:, others]]                     # [K, 3, 3]
+            top = np.all(np.isclose(fv[:, :, 2], L, rtol=0, atol=1e-12 * L),
+                         axis=1)
+            face_bc[:, f] = BC_ABSORBING
+            if top_free_surface:
+                face_bc[top, f] = BC_FREE_SURFACE
+    return {"vxyz": vxyz, "etov": etov, "vertex_periodic_id": pid,
+            "face_bc": face_bc, "n": n, "L": float(L), "h": h}
+
+
+def element_centroids(mesh):
+    """Mean of the 4 vertex coordinates of every element, [K, 3]."""
+    return mesh["vxyz"][mesh["etov"]].mean(axis=1)
+
+
+def lattice_node_coords(mesh, N):
+    """Physical coordinates of the nodal points, [K, Np, 3].
+
+    Node contract of the library: the equispaced lattice of order N on the
+    reference tetrahedron, node (i, j, k) with i + j + k <= N has barycentric
+    coordinates (1 - (i+j+k)/N, i/N, j/N, k/N) with respect to the element's
+    vertices (v0, v1, v2, v3); nodes are ordered k outermost, then j, then i.
+    """
+    lam = []
+    for k in range(N + 1):
+        for j in range(N + 1 - k):
+            for i in range(N + 1 - j - k):
+                lam.append((N - i - j - k, i, j, k))
+    lam = np.asarray(lam, dtype=np.float64) / N            # [Np, 4]
+    V = mesh["vxyz"][mesh["etov"]]                          # [K, 4, 3]
+    return np.einsum("na,kac->knc", lam, V)
