@@ -1,0 +1,199 @@
+/*
+ * dgw -- nodal discontinuous Galerkin solver for the isotropic
+ * velocity-stress elastic wave equation on affine tetrahedra, for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method.  The paper this library accompanies (arXiv 2205.11052) does not
+ * describe the discretisation, so every entry point states what it computes:
+ *
+ *   unknowns   q[k][c][n]: element k, field c in the order
+ *              (vx, vy, vz, sxx, syy, szz, syz, sxz, sxy), node n;
+ *   nodes      the equispaced lattice of order N on the reference tetrahedron
+ *              (-1,-1,-1),(1,-1,-1),(-1,1,-1),(-1,-1,1); node (i,j,k),
+ *              i+j+k <= N, at (r,s,t) = -1 + 2 (i,j,k)/N, ordered k outermost,
+ *              then j, then i (dgw_ref_nodes returns them);
+ *   faces      local face f is the face opposite local vertex f;
+ *   volume     strong form, rho v_t = div sigma,
+ *              sigma_t = lambda div(v) I + mu (grad v + grad v^T), with
+ *              element-constant rho, lambda, mu (nodal DG, Hesthaven and
+ *              Warburton, "Nodal Discontinuous Galerkin Methods", 2008);
+ *   faces      exact Riemann (upwind) flux of the elastic system normal to the
+ *              face with P impedance sqrt(rho (lambda + 2 mu)) on the normal
+ *              parts and S impedance sqrt(rho mu) on the tangential parts
+ *              (Wilcox, Stadler, Burstedde, Ghattas, J. Comput. Phys. 229,
+ *              2010), lifted to the element by the exact face mass matrices;
+ *   boundaries free surface (zero traction) and first-order absorbing
+ *              (no incoming characteristic); periodic faces are ordinary
+ *              neighbours;
+ *   time       five-stage fourth-order low-storage Runge-Kutta (Carpenter and
+ *              Kennedy, NASA TM-109112, 1994); the source time function is
+ *              evaluated at t_n + C_i dt in stage i;
+ *   source     moment-tensor point source M s(t) delta(x - x_s) added to the
+ *              stress equation, s the Ricker wavelet
+ *              amp (1 - 2 pi^2 f0^2 (t-t0)^2) exp(-pi^2 f0^2 (t-t0)^2);
+ *   receivers  velocity interpolated at each receiver after every step;
+ *   misfit     J = 1/2 dt sum_steps sum_receivers sum_xyz (trace - d)^2;
+ *   gradient   exact discrete adjoint of the time-stepping scheme with
+ *              respect to per-element rho, lambda, mu.
+ *
+ * Conventions for every entry point:
+ *   - Return value is a dgw_status; no C++ exception crosses the ABI.  On a
+ *     failure dgw_last_error() describes it.
+ *   - Host pointers are borrowed for the duration of the call only (the
+ *     library copies what it keeps).  Arrays are C order, FP64 unless stated.
+ *   - The context owns all device memory (allocated through the allocator
+ *     hook if one is set, else hipMalloc) and releases it in dgw_destroy.
+ *   - All device work is ordered on the context's stream; functions that
+ *     return data to the host synchronise that stream.
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef DGW_H
+#define DGW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dgw_ctx dgw_ctx;
+
+typedef enum dgw_status {
+  DGW_OK = 0,
+  DGW_EINVAL = -1,     /* invalid argument (null pointer, bad size/value)   */
+  DGW_ENOMEM = -2,     /* device or host allocation failed                 */
+  DGW_EMESH = -3,      /* invalid mesh: non-positive volume, non-manifold
+                          face, unmatched face without boundary tag        */
+  DGW_EHIP = -4,       /* a HIP runtime call failed (or no GPU present)    */
+  DGW_ESTATE = -5,     /* call made in the wrong order                     */
+  DGW_ERANGE = -6,     /* index or capacity out of range, point outside    */
+  DGW_ENONFINITE = -7  /* non-finite value detected in the fields          */
+} dgw_status;
+
+/* Create a context for polynomial order 1..6, precision 64 (FP64 fields and
+ * arithmetic) or 32 (FP32 fields and arithmetic, geometric factors kept in
+ * FP64 storage and converted in registers, reductions in FP64), and nshots
+ * independent shots sharing one mesh and medium.  hip_stream is a
+ * hipStream_t to order work on, or NULL for a stream owned by the library.
+ * No device memory is touched until dgw_set_mesh. */
+int dgw_create(int order, int precision, int nshots, void *hip_stream,
+               dgw_ctx **out);
+void dgw_destroy(dgw_ctx *ctx);
+const char *dgw_last_error(const dgw_ctx *ctx);
+
+/* Route device allocations through alloc(bytes, user) / free_(ptr, user)
+ * (for example a PyTorch caching allocator).  Must precede dgw_set_mesh. */
+int dgw_set_allocator(dgw_ctx *ctx, void *(*alloc)(size_t, void *),
+                      void (*free_)(void *, void *), void *user);
+
+/* Mesh upload.  vxyz [nvert][3]; etov [K][4] (0-based vertex ids, any
+ * orientation is accepted: negatively oriented elements are rejected with
+ * DGW_EMESH); vertex_periodic_id [nvert] or NULL: vertices with equal ids are
+ * identified when faces are matched (periodic meshes); face_bc [K][4] gives,
+ * for faces without a neighbour, 1 = free surface or 2 = absorbing (other
+ * values on such a face are DGW_EMESH; the value is ignored where a neighbour
+ * exists).  Faces are matched by the sorted triple of their (identified)
+ * vertex ids; a triple shared by more than two faces is DGW_EMESH. */
+int dgw_set_mesh(dgw_ctx *ctx, int64_t nvert, const double *vxyz, int64_t K,
+                 const int32_t *etov, const int32_t *vertex_periodic_id,
+                 const int8_t *face_bc);
+
+/* Per-element density and Lame parameters [K]; requires rho > 0, mu > 0,
+ * lambda + 2 mu / 3 > 0 and finite values (DGW_EINVAL otherwise). */
+int dgw_set_material(dgw_ctx *ctx, const double *rho, const double *lam,
+                     const double *mu);
+
+/* dt = cfl * 2 * min_k (r_k / cp_k) / (N+1)^2 with r_k = 3 V_k / sum_f A_f
+ * the inradius and cp_k = sqrt((lambda + 2 mu) / rho). */
+int dgw_suggest_dt(const dgw_ctx *ctx, double cfl, double *dt_out);
+int dgw_set_dt(dgw_ctx *ctx, double dt);
+
+/* Point source of shot `shot`: position xyz[3], moment tensor moment[6] in
+ * the order (xx, yy, zz, yz, xz, xy) (NULL = explosion, the identity), Ricker
+ * parameters f0, t0, amp; nsteps = the shot's length in steps (<= 0: no
+ * limit).  The delta is projected as (1/J) M^-1 l(r_s) onto the element that
+ * contains xyz (lowest element id among those whose barycentrics are all
+ * >= -1e-12; DGW_ERANGE when outside the mesh). */
+int dgw_set_source(dgw_ctx *ctx, int shot, const double *xyz,
+                   const double *moment, double f0, double t0, double amp,
+                   int64_t nsteps);
+
+/* Receivers of shot `shot`: xyz [nrec][3] located like the source; the trace
+ * buffer holds max_samples steps ([nrec][3][max_samples] velocities); a step
+ * that would exceed it makes dgw_step return DGW_ERANGE without stepping.
+ * Setting receivers clears the shot's traces. */
+int dgw_set_receivers(dgw_ctx *ctx, int shot, int nrec, const double *xyz,
+                      int64_t max_samples);
+
+/* Replace (set) or read (get) the fields of one shot, host layout
+ * q[K][9][Np] FP64 (converted for FP32 contexts).  dgw_set_fields also resets
+ * the shot's step counter and time to zero and clears its traces. */
+int dgw_set_fields(dgw_ctx *ctx, int shot, const double *q);
+int dgw_get_fields(dgw_ctx *ctx, int shot, double *q);
+
+/* Advance every shot that has steps left by up to nsteps steps (a shot stops
+ * at its length).  Each step is five fused RHS + LSERK stage launches and one
+ * receiver-sampling launch; batches of steps are replayed from a captured
+ * HIP graph. */
+int dgw_step(dgw_ctx *ctx, int64_t nsteps);
+
+/* Copy the recorded traces of one shot into out [nrec][3][cap] (the first n
+ * samples of each row are valid); *n = samples recorded so far. */
+int dgw_read_traces(dgw_ctx *ctx, int shot, double *out, int64_t cap,
+                    int64_t *n);
+
+/* Steps taken so far by a shot. */
+int dgw_shot_steps(dgw_ctx *ctx, int shot, int64_t *steps);
+
+/* Discrete energy of one shot,
+ * E = 1/2 sum_k J_k [rho v^T M v + sigma^T (S (x) M) sigma] with S the
+ * isotropic compliance, accumulated in FP64 on the device. */
+int dgw_energy(dgw_ctx *ctx, int shot, double *E);
+
+/* DGW_ENONFINITE if any field value of any shot is NaN or infinite. */
+int dgw_check_finite(dgw_ctx *ctx);
+
+/* Reference element of order N (host only, no context needed):
+ * rst [Np][3] node coordinates; Dr, Ds, Dt [Np][Np] (d l_n / dr at node i in
+ * row i, column n); M [Np][Np] the reference mass matrix (volume 4/3);
+ * LIFT [Np][4 Nfp] = M^-1 [E_0 .. E_3] with E_f the face mass matrix divided
+ * by the reference face area.  Any output pointer may be NULL. */
+int dgw_ref_nodes(int order, double *rst);
+int dgw_ref_operators(int order, double *Dr, double *Ds, double *Dt,
+                      double *M, double *LIFT);
+
+/* Differentiation.  dgw_forward_checkpointed runs every shot from its current
+ * state for nsteps steps, storing the state every ckpt_every steps in device
+ * memory, and returns the misfit of each shot against d_obs
+ * [nshots][nrec][3][nsteps] (misfit [nshots], accumulated in FP64).
+ * dgw_adjoint then computes, by the exact discrete adjoint with forward
+ * recomputation between checkpoints, the gradients of each shot's misfit with
+ * respect to rho, lambda, mu: g_* [nshots][K] FP64. */
+int dgw_forward_checkpointed(dgw_ctx *ctx, int64_t nsteps, int64_t ckpt_every,
+                             const double *d_obs, double *misfit);
+int dgw_adjoint(dgw_ctx *ctx, double *g_rho, double *g_lam, double *g_mu);
+
+/* Time the available launch shapes of the stage kernel on this context's
+ * workload and keep the fastest; if cache_path is not NULL the choice is read
+ * from / written to that JSON file (keyed by order, precision, element count
+ * and shot count).  *choice receives the chosen elements-per-block value. */
+int dgw_autotune(dgw_ctx *ctx, const char *cache_path, int *choice);
+
+/* Launch shape of the stage kernel: elements per work-group (0 = default).
+ * DGW_EINVAL for values the kernel does not implement. */
+int dgw_set_block(dgw_ctx *ctx, int elems_per_block);
+
+/* Average duration in milliseconds of the stage-kernel launches made by the
+ * last dgw_step call, measured with HIP events on the context's stream
+ * (0 if none was timed); enable with dgw_enable_timing(ctx, 1). */
+int dgw_enable_timing(dgw_ctx *ctx, int on);
+int dgw_stage_kernel_ms(dgw_ctx *ctx, double *ms, int64_t *launches);
+
+/* Sizes: Np = (N+1)(N+2)(N+3)/6 and Nfp = (N+1)(N+2)/2 of the context. */
+int dgw_sizes(const dgw_ctx *ctx, int *Np, int *Nfp, int64_t *K);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGW_H */

@@ -35,10 +35,11 @@ Kennedy, NASA TM-109112, 1994): for i = 1..5,
 res = A_i res + dt (L q + s(t_n + C_i dt)); q = q + B_i res; res = 0 at the
 start of each step.
 
-Source: explosive moment tensor (M = I) with Ricker time function
-s(tau) = amp (1 - 2 pi^2 f0^2 (tau - t0)^2) exp(-pi^2 f0^2 (tau - t0)^2),
-added to sxx, syy, szz of the source element as s(tau) / J M^-1 l(r_s)
-(the projection of a Dirac delta at the source point).
+Source: moment tensor M (default the explosion M = I) with Ricker time
+function s(tau) = amp (1 - 2 pi^2 f0^2 (tau - t0)^2) exp(-pi^2 f0^2 (tau - t0)^2),
+added to the stress components of the source element as
+M_c s(tau) / J M^-1 l(r_s) (the projection of a Dirac delta at the source
+point).
 
 Receivers: after every step, trace[r, c, n] = l(r_r) . v_c(k_r), c = x, y, z.
 
@@ -113,12 +114,14 @@ class Problem:
         self.receivers = None
 
     # --- sources and receivers -------------------------------------------
-    def set_source(self, xyz, f0, t0, amp=1.0):
+    def set_source(self, xyz, f0, t0, amp=1.0, moment=(1, 1, 1, 0, 0, 0)):
+        """Point source M s(t) delta(x - xyz); moment in the order
+        (xx, yy, zz, yz, xz, xy), default the explosion M = I."""
         k, rst = setup.locate(self.mesh, self.geo, np.asarray(xyz, float))
         ell = refelem.lagrange_at(self.N, rst)[0]
         vec = self.ops["Minv"] @ ell / self.geo["J"][k]
         self.source = dict(k=k, rst=rst, vec=torch.as_tensor(vec), f0=f0,
-                           t0=t0, amp=amp)
+                           t0=t0, amp=amp, moment=tuple(float(m) for m in moment))
 
     def set_receivers(self, xyz):
         xyz = np.atleast_2d(np.asarray(xyz, float))
@@ -231,8 +234,8 @@ def source_term(P, tau, dtype):
     if P.source is not None:
         s = P.source
         val = ricker(tau, s["f0"], s["t0"], s["amp"])
-        for c in (SXX, SYY, SZZ):
-            out[s["k"], c] = val * s["vec"].to(dtype)
+        for c, mc in zip((SXX, SYY, SZZ, SYZ, SXZ, SXY), s["moment"]):
+            out[s["k"], c] = val * mc * s["vec"].to(dtype)
     return out
 
 

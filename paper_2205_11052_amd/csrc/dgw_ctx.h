@@ -1,0 +1,97 @@
+// The library context (opaque to callers of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "dgw_internal.h"
+
+namespace dgw {
+const double *rk_a();
+const double *rk_b();
+const double *rk_c();
+}  // namespace dgw
+
+// Steps per captured HIP graph; even, so the ping-pong buffer roles are the
+// same before and after a replay.
+constexpr int kGraphSteps = 10;
+
+struct dgw_ctx {
+  int precision = 64;
+  int nshots = 1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool device_ready = false;
+  void *(*alloc_fn)(size_t, void *) = nullptr;
+  void (*free_fn)(void *, void *) = nullptr;
+  void *alloc_user = nullptr;
+  std::vector<void *> owned;
+  std::string err;
+
+  dgw::RefElem R;
+  dgw::MeshData mesh;
+  bool have_mesh = false, have_mat = false, have_dt = false;
+  double dt = 0;
+  std::vector<double> rho, lam, mu;
+
+  // device data
+  double *d_meta = nullptr;
+  int32_t *d_conn = nullptr, *d_nbtab = nullptr, *d_fmask = nullptr;
+  void *d_DrT = nullptr, *d_DsT = nullptr, *d_DtT = nullptr, *d_LIFTT = nullptr;
+  double *d_M = nullptr;
+  void *d_q[2] = {nullptr, nullptr};
+  void *d_res = nullptr;
+  int cur = 0;                      // buffer the next step reads from
+  std::vector<int> loc;             // per shot: buffer holding its state
+  int64_t *d_step = nullptr, *d_len = nullptr;
+  int32_t *d_src_elem = nullptr;
+  double *d_src_vec = nullptr, *d_src_par = nullptr;
+  std::vector<int64_t> h_step, h_len, h_cap_shot;
+  std::vector<int32_t> h_src_elem;
+  std::vector<double> h_src_vec, h_src_par;
+  int rmax = 0;
+  int64_t cap = 0;
+  int32_t *d_nrec = nullptr, *d_rec_elem = nullptr;
+  double *d_rec_w = nullptr, *d_trace = nullptr;
+  std::vector<int32_t> h_nrec, h_rec_elem;
+  std::vector<double> h_rec_w;
+  double *d_partial = nullptr;
+  int *d_flag = nullptr;
+
+  int block = 0;
+  hipGraphExec_t graph_exec = nullptr;
+  bool graph_ok = false;
+  int graph_from = 0;
+
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  int ev_pool_used = 0;
+  double timed_ms = 0;
+  int64_t timed_launches = 0;
+
+  // differentiation state (adjoint.cpp)
+  struct Adjoint;
+  Adjoint *adj = nullptr;
+
+  int fail(int code, const std::string &msg);
+  int hipfail(hipError_t e, const char *what);
+  void *dalloc(size_t bytes);
+  void dfree(void *p);
+  int ensure_device();
+  int upload(void *dst, const void *src, size_t bytes);
+  int download(void *dst, const void *src, size_t bytes);
+  size_t real_size() const;
+  void invalidate_graph();
+  int upload_operators();
+  int alloc_shots();
+  int sync_shot_tables();
+  int ensure_receivers(int need_r, int64_t need_cap);
+  int clear_traces(int shot);
+  int material_meta();
+  int enqueue_step(int from, bool timed);
+  int build_graph();
+  int gather_shots_to_cur(const std::vector<int64_t> &adv);
+  void free_adjoint();
+};

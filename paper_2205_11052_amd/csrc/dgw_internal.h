@@ -1,0 +1,115 @@
+// Internal declarations shared by the host setup, the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#define DGW_MAX_ORDER 6
+#define DGW_META 48   // doubles of per-element data (see MetaLayout)
+
+namespace dgw {
+
+// Per-element data, FP64, DGW_META doubles per element:
+//   [0..8]   X^-1 row-major (rx ry rz sx sy sz tx ty tz)
+//   [9..12]  Fscale_f = A_f / J
+//   [13..24] outward unit normals n_f (x, y, z)
+//   [25] 1/rho  [26] lambda  [27] mu  [28] Zp  [29] Zs
+//   [30..33] Zp of the neighbour across face f (own Zp on boundary faces)
+//   [34..37] Zs of the neighbour
+//   [38..41] 1 / (Zp + Zp_nb)   [42..45] 1 / (Zs + Zs_nb)
+//   [46] J   [47] unused
+enum MetaLayout {
+  M_XINV = 0, M_FSCALE = 9, M_NORMAL = 13, M_RHOINV = 25, M_LAM = 26,
+  M_MU = 27, M_ZP = 28, M_ZS = 29, M_ZPNB = 30, M_ZSNB = 34, M_IZPS = 38,
+  M_IZSS = 42, M_J = 46
+};
+
+// Packed face connectivity (int32 per element face): interior faces hold
+// (neighbour << 5) | (neighbour face << 3) | orientation (0..5); boundary
+// faces hold -1 (free surface) or -2 (absorbing).
+constexpr int CONN_FREE = -1;
+constexpr int CONN_ABSORB = -2;
+
+struct RefElem {
+  int N = 0, Np = 0, Nfp = 0;
+  std::vector<int> bary;   // [Np][4]
+  std::vector<int> fmask;  // [4][Nfp]
+  std::vector<double> rst, Dr, Ds, Dt, M, Minv, LIFT;
+};
+
+bool build_refelem(int N, RefElem &R);
+void eval_basis(const RefElem &R, const double rst[3], double *out);
+
+struct MeshData {
+  int64_t K = 0;
+  std::vector<double> vxyz;      // [nvert][3]
+  std::vector<int32_t> etov;     // [K][4]
+  std::vector<double> geo;       // [K][DGW_META] geometry part filled
+  std::vector<int32_t> conn;     // [K][4]
+  std::vector<int32_t> nbtab;    // [4][4][6][Nfp] neighbour volume node
+  std::vector<double> volume;    // [K]
+  std::vector<double> area;      // [K][4]
+};
+
+// Returns an empty string on success, else the reason.
+std::string build_mesh(const RefElem &R, int64_t nvert, const double *vxyz,
+                       int64_t K, const int32_t *etov, const int32_t *pid,
+                       const int8_t *face_bc, MeshData &out);
+// Element containing x (lowest id), reference coordinates; -1 if outside.
+int64_t locate_point(const MeshData &m, const double x[3], double rst[3]);
+
+// ---- device side -------------------------------------------------------
+
+template <typename real>
+struct StageArgs {
+  const real *q_in;
+  real *q_out;
+  real *res;
+  const double *meta;
+  const int32_t *conn;
+  const int32_t *nbtab;
+  const real *DrT, *DsT, *DtT;  // [j][i] (transposed)
+  const real *LIFTT;            // [4Nfp][Np] (transposed)
+  const int32_t *fmask;         // [4 Nfp]
+  int64_t K;
+  int64_t shot_stride;          // K * 9 * Np
+  const int64_t *shot_step;     // [S]
+  const int64_t *shot_len;      // [S]
+  const int32_t *src_elem;      // [S] (-1: none)
+  const double *src_vec;        // [S][Np]
+  const double *src_par;        // [S][10]: moment[6], f0, t0, amp, unused
+  double rk_a, rk_b, rk_c, dt;
+};
+
+struct RecArgs {
+  const void *q;                // current state (real)
+  int64_t shot_stride;
+  int Np;
+  const int32_t *nrec;          // [S]
+  int rmax;
+  const int32_t *rec_elem;      // [S][rmax]
+  const double *rec_w;          // [S][rmax][Np]
+  double *trace;                // [S][rmax][3][cap]
+  int64_t cap;
+  int64_t *shot_step;
+  const int64_t *shot_len;
+};
+
+// Launchers (kernels.hip); return the launch error.
+hipError_t launch_stage(int N, int precision, int be, int nshots,
+                        const void *args, hipStream_t st);
+hipError_t launch_receivers(int precision, int nshots, const RecArgs &a,
+                            hipStream_t st);
+hipError_t launch_energy(int precision, const void *q, int64_t K, int Np,
+                         const double *meta, const double *M, double *partial,
+                         int nblocks, hipStream_t st);
+hipError_t launch_finite(int precision, const void *q, int64_t n, int *flag,
+                         hipStream_t st);
+// Supported elements-per-block values for an order / precision.
+std::vector<int> stage_block_choices(int N, int precision);
+int default_block(int N, int precision);
+
+}  // namespace dgw

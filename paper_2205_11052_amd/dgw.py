@@ -1,0 +1,295 @@
+"""Python binding of the dgw C ABI (argument marshalling only).
+
+Every computation -- setup, stepping, receivers, energy, adjoint -- runs in
+libdgw.so; this module converts arrays, checks status codes and wires the
+PyTorch allocator and current stream into the library.
+"""
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+
+try:
+    import torch
+except ImportError:  # the binding itself does not need torch
+    torch = None
+
+
+class DGWError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_lib.STATUS.get(code, code), msg))
+        self.code = code
+        self.status = _lib.STATUS.get(code, str(code))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None and a.shape != tuple(shape):
+        a = a.reshape(shape)
+    return a
+
+
+def _host64(a):
+    if torch is not None and isinstance(a, torch.Tensor):
+        a = a.detach().to("cpu", torch.float64).numpy()
+    return _f64(a)
+
+
+def ref_nodes(order):
+    """Reference node coordinates [Np, 3] of the library's node contract."""
+    lib = _lib.load()
+    Np = (order + 1) * (order + 2) * (order + 3) // 6
+    out = np.empty((Np, 3))
+    rc = lib.dgw_ref_nodes(order, _dptr(out))
+    if rc:
+        raise DGWError(rc, "dgw_ref_nodes")
+    return out
+
+
+def ref_operators(order):
+    """(Dr, Ds, Dt, M, LIFT) as computed by the library's host setup."""
+    lib = _lib.load()
+    Np = (order + 1) * (order + 2) * (order + 3) // 6
+    Nfp = (order + 1) * (order + 2) // 2
+    Dr, Ds, Dt, M = (np.empty((Np, Np)) for _ in range(4))
+    LIFT = np.empty((Np, 4 * Nfp))
+    rc = lib.dgw_ref_operators(order, _dptr(Dr), _dptr(Ds), _dptr(Dt),
+                               _dptr(M), _dptr(LIFT))
+    if rc:
+        raise DGWError(rc, "dgw_ref_operators")
+    return Dr, Ds, Dt, M, LIFT
+
+
+class Solver:
+    """One dgw context: a mesh, a medium and ``nshots`` shots."""
+
+    def __init__(self, order, precision=64, nshots=1, stream=None,
+                 torch_allocator=None):
+        self.lib = _lib.load()
+        self.order = order
+        self.precision = precision
+        self.nshots = nshots
+        if stream is None and torch is not None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream().cuda_stream
+        self._ctx = C.c_void_p()
+        rc = self.lib.dgw_create(order, precision, nshots,
+                                 C.c_void_p(stream) if stream else None,
+                                 C.byref(self._ctx))
+        if rc:
+            raise DGWError(rc, "dgw_create(order=%s, precision=%s, nshots=%s)"
+                           % (order, precision, nshots))
+        if torch_allocator is None:
+            torch_allocator = torch is not None and torch.cuda.is_available()
+        self._callbacks = None
+        if torch_allocator:
+            self._use_torch_allocator()
+        self.Np = (order + 1) * (order + 2) * (order + 3) // 6
+        self.Nfp = (order + 1) * (order + 2) // 2
+        self.K = 0
+        self.nrec = [0] * nshots
+
+    # -- plumbing -------------------------------------------------------
+    def _check(self, rc, what):
+        if rc:
+            msg = self.lib.dgw_last_error(self._ctx)
+            raise DGWError(rc, "%s: %s" % (what, msg.decode() if msg else ""))
+
+    def _use_torch_allocator(self):
+        dev = torch.cuda.current_device()
+
+        def alloc(nbytes, user):
+            return torch.cuda.caching_allocator_alloc(
+                int(nbytes), dev, torch.cuda.current_stream(dev))
+
+        def free(ptr, user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._callbacks = (_lib.ALLOC_FN(alloc), _lib.FREE_FN(free))
+        self._check(self.lib.dgw_set_allocator(self._ctx, self._callbacks[0],
+                                               self._callbacks[1], None),
+                    "dgw_set_allocator")
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self.lib.dgw_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setup ------------------------------------------------------------
+    def set_mesh(self, vxyz, etov, vertex_periodic_id=None, face_bc=None):
+        vxyz = _f64(vxyz)
+        etov = np.ascontiguousarray(np.asarray(etov, dtype=np.int32))
+        pid = None
+        if vertex_periodic_id is not None:
+            pid = np.ascontiguousarray(np.asarray(vertex_periodic_id, np.int32))
+        bc = None
+        if face_bc is not None:
+            bc = np.ascontiguousarray(np.asarray(face_bc, dtype=np.int8))
+        self._check(self.lib.dgw_set_mesh(
+            self._ctx, vxyz.shape[0], _dptr(vxyz), etov.shape[0],
+            etov.ctypes.data_as(C.POINTER(C.c_int32)),
+            pid.ctypes.data_as(C.POINTER(C.c_int32)) if pid is not None else None,
+            bc.ctypes.data_as(C.POINTER(C.c_int8)) if bc is not None else None),
+            "dgw_set_mesh")
+        self.K = etov.shape[0]
+
+    def set_mesh_dict(self, mesh):
+        self.set_mesh(mesh["vxyz"], mesh["etov"], mesh.get("vertex_periodic_id"),
+                      mesh.get("face_bc"))
+
+    def set_material(self, rho, lam, mu):
+        r, l, m = _host64(rho), _host64(lam), _host64(mu)
+        self._check(self.lib.dgw_set_material(self._ctx, _dptr(r), _dptr(l),
+                                              _dptr(m)), "dgw_set_material")
+
+    def suggest_dt(self, cfl):
+        out = C.c_double()
+        self._check(self.lib.dgw_suggest_dt(self._ctx, cfl, C.byref(out)),
+                    "dgw_suggest_dt")
+        return out.value
+
+    def set_dt(self, dt):
+        self._check(self.lib.dgw_set_dt(self._ctx, float(dt)), "dgw_set_dt")
+        self.dt = float(dt)
+
+    def set_source(self, shot, xyz, f0, t0, amp=1.0, nsteps=0, moment=None):
+        x = _f64(xyz)
+        m = _f64(moment) if moment is not None else None
+        self._check(self.lib.dgw_set_source(
+            self._ctx, shot, _dptr(x), _dptr(m) if m is not None else None,
+            float(f0), float(t0), float(amp), int(nsteps)), "dgw_set_source")
+
+    def set_receivers(self, shot, xyz, max_samples):
+        x = _f64(xyz).reshape(-1, 3)
+        self._check(self.lib.dgw_set_receivers(self._ctx, shot, x.shape[0],
+                                               _dptr(x), int(max_samples)),
+                    "dgw_set_receivers")
+        self.nrec[shot] = x.shape[0]
+
+    def set_fields(self, shot, q):
+        q = _host64(q)
+        if q.size != self.K * 9 * self.Np:
+            raise ValueError("fields must have K*9*Np entries")
+        self._check(self.lib.dgw_set_fields(self._ctx, shot, _dptr(q)),
+                    "dgw_set_fields")
+
+    def zero_fields(self):
+        z = np.zeros((self.K, 9, self.Np))
+        for s in range(self.nshots):
+            self.set_fields(s, z)
+
+    def get_fields(self, shot):
+        out = np.empty((self.K, 9, self.Np))
+        self._check(self.lib.dgw_get_fields(self._ctx, shot, _dptr(out)),
+                    "dgw_get_fields")
+        return out
+
+    # -- stepping ---------------------------------------------------------
+    def step(self, nsteps):
+        self._check(self.lib.dgw_step(self._ctx, int(nsteps)), "dgw_step")
+
+    def shot_steps(self, shot):
+        n = C.c_int64()
+        self._check(self.lib.dgw_shot_steps(self._ctx, shot, C.byref(n)),
+                    "dgw_shot_steps")
+        return n.value
+
+    def read_traces(self, shot):
+        n = C.c_int64()
+        self._check(self.lib.dgw_read_traces(self._ctx, shot, None, 0,
+                                             C.byref(n)), "dgw_read_traces")
+        nr = self.nrec[shot]
+        out = np.zeros((nr, 3, max(n.value, 1)))
+        if nr and n.value:
+            self._check(self.lib.dgw_read_traces(self._ctx, shot, _dptr(out),
+                                                 out.shape[2], C.byref(n)),
+                        "dgw_read_traces")
+        return out[:, :, :n.value]
+
+    def energy(self, shot=0):
+        e = C.c_double()
+        self._check(self.lib.dgw_energy(self._ctx, shot, C.byref(e)),
+                    "dgw_energy")
+        return e.value
+
+    def check_finite(self):
+        self._check(self.lib.dgw_check_finite(self._ctx), "dgw_check_finite")
+
+    # -- differentiation --------------------------------------------------
+    def forward_checkpointed(self, nsteps, ckpt_every, d_obs):
+        d = _host64(d_obs)
+        mis = np.empty(self.nshots)
+        self._check(self.lib.dgw_forward_checkpointed(
+            self._ctx, int(nsteps), int(ckpt_every), _dptr(d), _dptr(mis)),
+            "dgw_forward_checkpointed")
+        return mis
+
+    def adjoint(self):
+        g = [np.empty((self.nshots, self.K)) for _ in range(3)]
+        self._check(self.lib.dgw_adjoint(self._ctx, _dptr(g[0]), _dptr(g[1]),
+                                         _dptr(g[2])), "dgw_adjoint")
+        return g
+
+    # -- launch shape and timing ---------------------------------------------
+    def autotune(self, cache_path=None):
+        ch = C.c_int()
+        self._check(self.lib.dgw_autotune(
+            self._ctx, cache_path.encode() if cache_path else None,
+            C.byref(ch)), "dgw_autotune")
+        return ch.value
+
+    def set_block(self, elems):
+        self._check(self.lib.dgw_set_block(self._ctx, int(elems)),
+                    "dgw_set_block")
+
+    def enable_timing(self, on=True):
+        self._check(self.lib.dgw_enable_timing(self._ctx, 1 if on else 0),
+                    "dgw_enable_timing")
+
+    def stage_kernel_ms(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(self.lib.dgw_stage_kernel_ms(self._ctx, C.byref(ms),
+                                                 C.byref(n)),
+                    "dgw_stage_kernel_ms")
+        return ms.value, n.value
+
+
+if torch is not None:
+    class ElasticMisfit(torch.autograd.Function):
+        """misfit[s] = 1/2 dt sum (trace_s - d_obs[s])^2 as a function of the
+        per-element rho, lambda, mu; backward runs the library's discrete
+        adjoint (with checkpointed forward recomputation).
+
+        apply(rho, lam, mu, solver, d_obs, nsteps, ckpt_every) -> [nshots]
+        Every shot starts from zero fields."""
+
+        @staticmethod
+        def forward(ctx, rho, lam, mu, solver, d_obs, nsteps, ckpt_every):
+            solver.set_material(rho, lam, mu)
+            solver.zero_fields()
+            mis = solver.forward_checkpointed(nsteps, ckpt_every, d_obs)
+            ctx.solver = solver
+            ctx.device = rho.device
+            return torch.as_tensor(mis, dtype=torch.float64, device=rho.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = ctx.solver.adjoint()
+            w = grad_out.detach().to("cpu", torch.float64).numpy()
+            outs = [torch.as_tensor((w[:, None] * gi).sum(axis=0),
+                                    device=ctx.device) for gi in g]
+            return outs[0], outs[1], outs[2], None, None, None, None
+else:
+    ElasticMisfit = None

@@ -1,0 +1,242 @@
+"""GPU parity of the forward solver (FP64 and FP32) against the CPU oracle.
+
+All calls go through the C ABI (libdgw.so) via the ctypes binding.  Bars:
+FP64 relative L2 <= 1e-12, FP32 relative L2 <= 1e-5 against the FP64 oracle
+on the same seeded inputs.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_helpers import (gpu_solver, oracle_problem, oracle_run, rel_l2,
+                         random_fields, say)
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def _random_medium(K, seed):
+    rng = np.random.default_rng(seed)
+    cp = rng.uniform(1.5, 3.0, K)
+    cs = cp / rng.uniform(1.5, 2.2, K)
+    rho = rng.uniform(1.0, 3.0, K)
+    return W.lame_from_velocities(cp, cs, rho)
+
+
+def test_c0_periodic_plane_wave_fp64():
+    w = W.build_workload("c0_periodic_pwave")
+    say("case c0_periodic_pwave fp64 K=%d N=%d" % (w["K"], w["N"]))
+    P = oracle_problem(w["mesh"], w["N"])
+    dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
+    s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
+    assert abs(s.suggest_dt(w["cfl"]) - dt) <= 1e-14 * dt
+    s.set_fields(0, w["q0"])
+    s.step(w["steps"])
+    q_gpu = s.get_fields(0)
+    q_ora, _ = oracle_run(P, w["q0"], w["rho"], w["lam"], w["mu"], dt,
+                          w["steps"])
+    err = rel_l2(q_gpu, q_ora)
+    say("c0 fp64 rel L2 vs oracle", err)
+    assert err <= FP64_TOL
+    # discrete energy on the device equals the oracle's
+    from oracle import solver as O
+    t = lambda a: torch.as_tensor(np.asarray(a))
+    e_ora = O.energy(P, t(q_ora), t(w["rho"]), t(w["lam"]), t(w["mu"])).item()
+    assert abs(s.energy(0) - e_ora) <= 1e-13 * e_ora
+    s.check_finite()
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6])
+def test_all_orders_all_boundaries_fp64(N):
+    mesh = W.kuhn_cube(2, 1.0)          # free-surface top, absorbing sides
+    K = mesh["etov"].shape[0]
+    rho, lam, mu = _random_medium(K, 100 + N)
+    say("case orders fp64 N=%d K=%d" % (N, K))
+    P = oracle_problem(mesh, N)
+    dt = P.suggest_dt(rho, lam, mu, 0.5)
+    q0 = random_fields(K, P.Np, 200 + N)
+    src = np.array([0.37, 0.52, 0.61])
+    moment = (1.0, -0.5, 0.25, 0.3, -0.2, 0.1)
+    rec = np.array([[0.2, 0.3, 1.0], [0.8, 0.6, 0.5], [0.1, 0.9, 0.0]])
+    P.set_source(src, 3.0, 0.1, 2.0, moment=moment)
+    P.set_receivers(rec)
+    s = gpu_solver(mesh, N, rho, lam, mu, dt)
+    s.set_source(0, src, 3.0, 0.1, 2.0, moment=moment)
+    s.set_receivers(0, rec, 16)
+    s.set_fields(0, q0)
+    nst = 7
+    s.step(nst)
+    q_ora, tr_ora = oracle_run(P, q0, rho, lam, mu, dt, nst, record=True)
+    err = rel_l2(s.get_fields(0), q_ora)
+    terr = rel_l2(s.read_traces(0), tr_ora)
+    say("N=%d fields %.3e traces %.3e" % (N, err, terr))
+    assert err <= FP64_TOL and terr <= FP64_TOL
+    assert s.shot_steps(0) == nst
+
+
+def _reduced_c1(n=6, N=4, t0=0.35):
+    w = W.build_workload("c1_layered_n24", n=n, N=N)
+    w["t0"] = t0
+    return w
+
+
+def test_reduced_layered_source_receivers_fp64():
+    w = _reduced_c1()
+    say("case reduced c1 fp64 K=%d" % w["K"])
+    P = oracle_problem(w["mesh"], w["N"])
+    dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
+    P.set_source(w["source"], w["f0"], w["t0"], w["amp"])
+    P.set_receivers(w["receivers"])
+    nst = 40
+    s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
+    s.set_source(0, w["source"], w["f0"], w["t0"], w["amp"])
+    s.set_receivers(0, w["receivers"], nst)
+    s.step(nst)
+    q_ora, tr_ora = oracle_run(P, np.zeros((w["K"], 9, P.Np)), w["rho"],
+                               w["lam"], w["mu"], dt, nst, record=True)
+    err = rel_l2(s.get_fields(0), q_ora)
+    tr = s.read_traces(0)
+    terr = np.abs(tr - tr_ora).max() / np.abs(tr_ora).max()
+    say("reduced c1 fields %.3e traces %.3e" % (err, terr))
+    assert np.abs(q_ora).max() > 0 and np.abs(tr_ora).max() > 0
+    assert err <= FP64_TOL and terr <= FP64_TOL
+
+
+def test_full_size_layered_fp64_bench_launch():
+    """Full 82944-element mesh at order 4 in the benchmark's launch shape:
+    random fields everywhere (every face type and element exercised), the
+    source and receivers active, two steps against the oracle."""
+    w = W.build_workload("c1_layered_n24")
+    say("case full c1 fp64 K=%d" % w["K"])
+    P = oracle_problem(w["mesh"], w["N"])
+    dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
+    P.set_source(w["source"], w["f0"], 0.05, w["amp"])
+    P.set_receivers(w["receivers"])
+    q0 = random_fields(w["K"], P.Np, 7)
+    s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
+    s.set_source(0, w["source"], w["f0"], 0.05, w["amp"])
+    s.set_receivers(0, w["receivers"], 8)
+    s.set_fields(0, q0)
+    s.step(2)
+    q_gpu = s.get_fields(0)
+    tr = s.read_traces(0)
+    q_ora, tr_ora = oracle_run(P, q0, w["rho"], w["lam"], w["mu"], dt, 2,
+                               record=True)
+    err = rel_l2(q_gpu, q_ora)
+    terr = rel_l2(tr, tr_ora)
+    say("full c1 fields %.3e traces %.3e" % (err, terr))
+    assert err <= FP64_TOL and terr <= FP64_TOL
+
+
+def test_fp32_error_against_fp64_oracle():
+    w = W.build_workload("c0_periodic_pwave")
+    say("case c0 fp32")
+    P = oracle_problem(w["mesh"], w["N"])
+    dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
+    s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt, 32)
+    s.set_fields(0, w["q0"])
+    s.step(w["steps"])
+    q_ora, _ = oracle_run(P, w["q0"], w["rho"], w["lam"], w["mu"], dt,
+                          w["steps"])
+    err = rel_l2(s.get_fields(0), q_ora)
+    say("c0 fp32 rel L2 vs fp64 oracle %.3e" % err)
+    assert err <= FP32_TOL
+
+
+@pytest.mark.parametrize("N", [4, 6])
+def test_fp32_reduced_layered(N):
+    w = _reduced_c1(n=4, N=N)
+    say("case reduced c2 fp32 N=%d K=%d" % (N, w["K"]))
+    P = oracle_problem(w["mesh"], w["N"])
+    dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
+    P.set_source(w["source"], w["f0"], w["t0"], w["amp"])
+    P.set_receivers(w["receivers"])
+    q0 = random_fields(w["K"], P.Np, 31)
+    nst = 10
+    s = gpu_solver(w["mesh"], N, w["rho"], w["lam"], w["mu"], dt, 32)
+    s.set_source(0, w["source"], w["f0"], w["t0"], w["amp"])
+    s.set_receivers(0, w["receivers"], nst)
+    s.set_fields(0, q0)
+    s.step(nst)
+    q_ora, tr_ora = oracle_run(P, q0, w["rho"], w["lam"], w["mu"], dt, nst,
+                               record=True)
+    err = rel_l2(s.get_fields(0), q_ora)
+    terr = rel_l2(s.read_traces(0), tr_ora)
+    say("fp32 N=%d fields %.3e traces %.3e" % (N, err, terr))
+    assert err <= FP32_TOL and terr <= FP32_TOL
+
+
+def test_graph_replay_equals_eager_and_block_shapes_agree():
+    w = _reduced_c1(n=4)
+    say("case graph vs eager")
+    P = oracle_problem(w["mesh"], w["N"])
+    dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
+    q0 = random_fields(w["K"], P.Np, 5)
+    outs = []
+    for timing, block in ((False, 0), (True, 0), (False, 4)):
+        s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
+        s.set_block(block)
+        s.enable_timing(timing)
+        s.set_source(0, w["source"], w["f0"], w["t0"], w["amp"])
+        s.set_fields(0, q0)
+        s.step(23)
+        outs.append(s.get_fields(0))
+        if timing:
+            ms, n = s.stage_kernel_ms()
+            assert n == 5 * 23 and ms > 0
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_batched_shots_match_single_shot_runs(precision):
+    mesh = W.kuhn_cube(3, 1.0)
+    K = mesh["etov"].shape[0]
+    rho, lam, mu = _random_medium(K, 3)
+    N = 3
+    dt = 0.5 * 2 * (1 / 3) / (2 * (1 + np.sqrt(2))) / np.sqrt(
+        np.max((lam + 2 * mu) / rho)) / 16
+    srcs = np.array([[0.2, 0.3, 0.4], [0.7, 0.6, 0.5], [0.5, 0.5, 0.9]])
+    lens = [7, 12, 3]
+    rec = np.array([[0.4, 0.4, 1.0], [0.6, 0.2, 1.0]])
+    say("case batched shots precision=%d" % precision)
+    b = gpu_solver(mesh, N, rho, lam, mu, dt, precision, nshots=3)
+    for i in range(3):
+        b.set_source(i, srcs[i], 6.0, 0.1, 1.0, nsteps=lens[i])
+        b.set_receivers(i, rec, 20)
+    b.step(15)
+    for i in range(3):
+        assert b.shot_steps(i) == lens[i]
+        one = gpu_solver(mesh, N, rho, lam, mu, dt, precision)
+        one.set_source(0, srcs[i], 6.0, 0.1, 1.0, nsteps=lens[i])
+        one.set_receivers(0, rec, 20)
+        one.step(15)
+        assert np.array_equal(b.get_fields(i), one.get_fields(0))
+        tb, to = b.read_traces(i), one.read_traces(0)
+        assert tb.shape == (2, 3, lens[i]) and np.array_equal(tb, to)
+    # a shot extended after it stopped resumes from its own state
+    b.set_source(2, srcs[2], 6.0, 0.1, 1.0, nsteps=5)
+    b.step(2)
+    assert b.shot_steps(2) == 5 and b.shot_steps(0) == 7
+
+
+def test_tiny_mesh_smaller_than_a_block_and_zero_steps():
+    mesh = W.kuhn_cube(1, 1.0)
+    K = mesh["etov"].shape[0]
+    rho, lam, mu = _random_medium(K, 8)
+    say("case tiny mesh")
+    for N in (1, 4):
+        P = oracle_problem(mesh, N)
+        dt = P.suggest_dt(rho, lam, mu, 0.5)
+        q0 = random_fields(K, P.Np, 9)
+        s = gpu_solver(mesh, N, rho, lam, mu, dt)
+        s.set_fields(0, q0)
+        s.step(0)
+        assert np.array_equal(s.get_fields(0), q0)
+        s.step(3)
+        q_ora, _ = oracle_run(P, q0, rho, lam, mu, dt, 3)
+        assert rel_l2(s.get_fields(0), q_ora) <= FP64_TOL
