@@ -1,0 +1,196 @@
+"""Benchmark of the fused nodal-DG elastic RHS + LSERK4 stage on one MI355X.
+
+Workload (the headline configuration): the [0,10]^3 cube split into
+6*24^3 = 82944 tetrahedra, order 4 (35 nodes, 9 fields = 26,127,360 DOF),
+FP64, layered noisy medium, free-surface top and absorbing sides, explosive
+Ricker point source and 64 surface receivers.  One "step" is one LSERK4 time
+step: five fused stage launches plus one receiver-sampling launch.  Fields are
+resident in HBM before the timed region; the timed region replays captured
+HIP graphs on a torch stream bracketed by torch.cuda.synchronize() and HIP
+events.
+
+Metric: GDOF-stage/s = 9 * Np * K * 5 * steps / seconds / 1e9.
+
+Extra forms reported beside the headline (same GPU, same mesh and medium):
+FP32 fields and arithmetic, and a batch of 32 FP32 shots advanced together.
+
+Roofline: the stage kernel's algorithmic HBM bytes per launch (read q and
+res, write res and q', read the per-element data and connectivity) divided by
+its average launch duration, timed with HIP events around each launch on the
+library's stream, against 8 TB/s.
+
+CPU baseline: the CPU oracle (plain PyTorch FP64) timed on the host on a
+bounded sample of the same workload (two LSERK4 steps of the full mesh).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+META_BYTES = 48 * 8 + 4 * 4        # per-element data + packed connectivity
+
+
+def stage_bytes(K, Np, real_bytes, nshots=1):
+    """Algorithmic HBM bytes of one stage launch: q and res read, res and q'
+    written (4 field streams), per-element data and connectivity read once."""
+    return nshots * K * 4 * 9 * Np * real_bytes + K * META_BYTES
+
+
+def build_solver(w, precision, nshots=1, stream=None, shots=None):
+    from paper_2205_11052_amd import Solver
+    s = Solver(w["N"], precision, nshots, stream=stream)
+    s.set_mesh_dict(w["mesh"])
+    s.set_material(w["rho"], w["lam"], w["mu"])
+    dt = s.suggest_dt(w["cfl"])
+    s.set_dt(dt)
+    for i in range(nshots):
+        pos = w["source"] if shots is None else shots[0][i]
+        n = 0 if shots is None else int(shots[1][i])
+        s.set_source(i, pos, w["f0"], w["t0"], w["amp"], nsteps=n)
+        s.set_receivers(i, w["receivers"], 4096)
+    return s
+
+
+def timed_steps(torch, s, stream, steps, warmup):
+    s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    t0.record(stream)
+    s.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    return t0.elapsed_time(t1) / 1000.0, wall
+
+
+def kernel_avg_ms(s, steps=10):
+    s.enable_timing(True)
+    s.step(steps)
+    ms, n = s.stage_kernel_ms()
+    s.enable_timing(False)
+    return ms, n
+
+
+def cpu_baseline(w, steps=2):
+    import torch
+    from oracle import solver as O
+    P = O.Problem(w["mesh"], w["N"])
+    t = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64))
+    P.set_source(w["source"], w["f0"], w["t0"], w["amp"])
+    q = torch.zeros(w["K"], 9, P.Np, dtype=torch.float64)
+    dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
+    rho, lam, mu = t(w["rho"]), t(w["lam"]), t(w["mu"])
+    O.lserk_step(P, q, 0.0, dt, rho, lam, mu)       # warm-up
+    t0 = time.perf_counter()
+    for s_ in range(steps):
+        q = O.lserk_step(P, q, s_ * dt, dt, rho, lam, mu)
+    sec = time.perf_counter() - t0
+    dof = 9 * P.Np * w["K"]
+    return {"value": dof * 5 * steps / sec / 1e9, "unit": "GDOF-stage/s",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": "%d LSERK4 steps (%d stages) of the full 82944-element "
+                      "order-4 FP64 workload, %.2f s" % (steps, 5 * steps, sec)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--block", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU "
+              "path (the mesh-partition design is documented, not built).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    w = W.build_workload("c1_layered_n24")
+    K, N = w["K"], w["N"]
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    dof = 9 * Np * K
+
+    with torch.cuda.stream(stream):
+        s = build_solver(w, 64, stream=stream.cuda_stream)
+        if args.block:
+            s.set_block(args.block)
+        sec, wall = timed_steps(torch, s, stream, args.steps, args.warmup)
+        kms, nl = kernel_avg_ms(s)
+        s.check_finite()
+    value = dof * 5 * args.steps / sec / 1e9
+    bytes_launch = stage_bytes(K, Np, 8)
+    achieved = bytes_launch / (kms / 1e3) / 1e9
+    out = {
+        "metric": "GDOF-stage/s", "value": round(value, 3),
+        "unit": "GDOF-stage/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sec / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "c1_layered_n24", "elements": K, "order": N,
+                   "nodes_per_element": Np, "dof": dof, "shots": 1,
+                   "stages_per_step": 5, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "kernel": "stage_kernel<4,double>",
+                     "kernel_avg_ms": round(kms, 5),
+                     "launches_timed": nl,
+                     "bytes_per_launch": bytes_launch},
+    }
+    del s
+    if not args.no_forms:
+        forms = {}
+        with torch.cuda.stream(stream):
+            s32 = build_solver(w, 32, stream=stream.cuda_stream)
+            sec32, _ = timed_steps(torch, s32, stream, args.steps, args.warmup)
+            k32, _ = kernel_avg_ms(s32)
+        del s32
+        forms["fp32"] = {
+            "value": round(dof * 5 * args.steps / sec32 / 1e9, 3),
+            "ms_per_step": round(sec32 / args.steps * 1e3, 4),
+            "speedup_vs_fp64": round(sec / sec32, 3),
+            "kernel_avg_ms": round(k32, 5),
+            "hbm_frac": round(stage_bytes(K, Np, 4) / (k32 / 1e3) / 1e9
+                              / HBM_PEAK_GBS, 4)}
+        pos, lens = W.batched_shots()
+        nb = len(pos)
+        bsteps = max(10, args.steps // 10)
+        with torch.cuda.stream(stream):
+            sb = build_solver(w, 32, nshots=nb, stream=stream.cuda_stream,
+                              shots=(pos, lens))
+            secb, _ = timed_steps(torch, sb, stream, bsteps, 2)
+        del sb
+        forms["fp32_batched_32_shots"] = {
+            "value": round(nb * dof * 5 * bsteps / secb / 1e9, 3),
+            "ms_per_step": round(secb / bsteps * 1e3, 4),
+            "steps": bsteps,
+            "speedup_vs_fp64": round((nb * bsteps / secb)
+                                     / (args.steps / sec), 3)}
+        out["forms"] = forms
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,25 +1,353 @@
-// Discrete adjoint (placeholder until the adjoint kernels land).
+// Checkpointed forward run and reverse (adjoint) sweep of the C ABI.
+//
+// Forward: every shot runs from its (step 0) state for nsteps steps through
+// the ordinary stepping path; the state of every shot is copied to a device
+// checkpoint every ckpt_every steps; traces are recorded as usual and the
+// misfit is reduced on the host in FP64.
+// Reverse: segments are visited last to first; a segment is recomputed from
+// its checkpoint, storing every step-start state; then for each step, last
+// to first: the receiver residual is injected into lam_q, the step's five
+// stage inputs are recomputed, and the five stages are reversed (adjoint
+// launches).  The gradient accumulates per element in FP64 on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
 #include "../../include/dgw.h"
 #include "dgw_ctx.h"
 
-struct dgw_ctx::Adjoint {};
+using namespace dgw;
+
+struct dgw_ctx::Adjoint {
+  bool ready = false;
+  int64_t nsteps = 0, every = 0;
+  std::vector<void *> ckpt;     // per checkpoint: [S][K][9][Np]
+  double *d_obs = nullptr;      // [S][rmax][3][nsteps]
+  int64_t *d_aux = nullptr;     // per-shot step used by recomputation
+  // adjoint operators (row-major D, LIFT) and tables
+  void *d_Dr = nullptr, *d_Ds = nullptr, *d_Dt = nullptr, *d_LIFT = nullptr;
+  int32_t *d_facepos = nullptr, *d_nbface = nullptr;
+};
 
 void dgw_ctx::free_adjoint() {
+  if (!adj) return;
+  for (void *p : adj->ckpt) dfree(p);
+  dfree(adj->d_obs);
+  dfree(adj->d_aux);
+  dfree(adj->d_Dr);
+  dfree(adj->d_Ds);
+  dfree(adj->d_Dt);
+  dfree(adj->d_LIFT);
+  dfree(adj->d_facepos);
+  dfree(adj->d_nbface);
   delete adj;
   adj = nullptr;
 }
 
+namespace {
+
+template <typename real>
+int upload_real(dgw_ctx *c, void **dst, const std::vector<double> &src) {
+  std::vector<real> tmp(src.begin(), src.end());
+  *dst = c->dalloc(sizeof(real) * tmp.size());
+  if (!*dst) return c->fail(DGW_ENOMEM, "device allocation failed (adjoint operators)");
+  return c->upload(*dst, tmp.data(), sizeof(real) * tmp.size());
+}
+
+int upload_adjoint_tables(dgw_ctx *c) {
+  dgw_ctx::Adjoint *a = c->adj;
+  if (a->d_Dr) return DGW_OK;
+  int rc;
+  if (c->precision == 64) {
+    if ((rc = upload_real<double>(c, &a->d_Dr, c->R.Dr))) return rc;
+    if ((rc = upload_real<double>(c, &a->d_Ds, c->R.Ds))) return rc;
+    if ((rc = upload_real<double>(c, &a->d_Dt, c->R.Dt))) return rc;
+    if ((rc = upload_real<double>(c, &a->d_LIFT, c->R.LIFT))) return rc;
+  } else {
+    if ((rc = upload_real<float>(c, &a->d_Dr, c->R.Dr))) return rc;
+    if ((rc = upload_real<float>(c, &a->d_Ds, c->R.Ds))) return rc;
+    if ((rc = upload_real<float>(c, &a->d_Dt, c->R.Dt))) return rc;
+    if ((rc = upload_real<float>(c, &a->d_LIFT, c->R.LIFT))) return rc;
+  }
+  const int Np = c->R.Np, Nfp = c->R.Nfp;
+  std::vector<int32_t> fp(4 * Np, -1);
+  for (int f = 0; f < 4; ++f)
+    for (int m = 0; m < Nfp; ++m) fp[f * Np + c->R.fmask[f * Nfp + m]] = m;
+  a->d_facepos = (int32_t *)c->dalloc(sizeof(int32_t) * fp.size());
+  a->d_nbface = (int32_t *)c->dalloc(sizeof(int32_t) * c->mesh.nbface.size());
+  if (!a->d_facepos || !a->d_nbface)
+    return c->fail(DGW_ENOMEM, "device allocation failed (adjoint tables)");
+  if ((rc = c->upload(a->d_facepos, fp.data(), sizeof(int32_t) * fp.size()))) return rc;
+  return c->upload(a->d_nbface, c->mesh.nbface.data(),
+                   sizeof(int32_t) * c->mesh.nbface.size());
+}
+
+template <typename real>
+void fill_adj(dgw_ctx *c, AdjArgs<real> &a, const void *q, void *lq, void *lr,
+              void *zbuf, double *grad, int stage) {
+  a.q = (const real *)q;
+  a.lam_q = (real *)lq;
+  a.lam_r = (real *)lr;
+  a.zbuf = (real *)zbuf;
+  a.grad = grad;
+  a.meta = c->d_meta;
+  a.conn = c->d_conn;
+  a.nbtab = c->d_nbtab;
+  a.nbface = c->adj->d_nbface;
+  a.DrT = (const real *)c->d_DrT;
+  a.DsT = (const real *)c->d_DsT;
+  a.DtT = (const real *)c->d_DtT;
+  a.Dr = (const real *)c->adj->d_Dr;
+  a.Ds = (const real *)c->adj->d_Ds;
+  a.Dt = (const real *)c->adj->d_Dt;
+  a.LIFT = (const real *)c->adj->d_LIFT;
+  a.fmask = c->d_fmask;
+  a.facepos = c->adj->d_facepos;
+  a.K = c->mesh.K;
+  a.shot_stride = c->mesh.K * 9 * c->R.Np;
+  a.shot_step = c->adj->d_aux;
+  a.shot_len = c->d_len;
+  a.rk_a = rk_a()[stage];
+  a.rk_b = rk_b()[stage];
+  a.dt = c->dt;
+}
+
+template <typename real>
+void fill_stage(dgw_ctx *c, StageArgs<real> &a, const void *in, void *out,
+                void *res, int stage) {
+  a.q_in = (const real *)in;
+  a.q_out = (real *)out;
+  a.res = (real *)res;
+  a.meta = c->d_meta;
+  a.conn = c->d_conn;
+  a.nbtab = c->d_nbtab;
+  a.DrT = (const real *)c->d_DrT;
+  a.DsT = (const real *)c->d_DsT;
+  a.DtT = (const real *)c->d_DtT;
+  a.LIFTT = (const real *)c->d_LIFTT;
+  a.fmask = c->d_fmask;
+  a.K = c->mesh.K;
+  a.shot_stride = c->mesh.K * 9 * c->R.Np;
+  a.shot_step = c->adj->d_aux;
+  a.shot_len = c->d_len;
+  a.src_elem = c->d_src_elem;
+  a.src_vec = c->d_src_vec;
+  a.src_par = c->d_src_par;
+  a.rk_a = rk_a()[stage];
+  a.rk_b = rk_b()[stage];
+  a.rk_c = rk_c()[stage];
+  a.dt = c->dt;
+}
+
+int stage_explicit(dgw_ctx *c, const void *in, void *out, void *res, int stage) {
+  hipError_t e;
+  if (c->precision == 64) {
+    StageArgs<double> a;
+    fill_stage(c, a, in, out, res, stage);
+    e = launch_stage(c->R.N, 64, c->block, c->nshots, &a, c->stream);
+  } else {
+    StageArgs<float> a;
+    fill_stage(c, a, in, out, res, stage);
+    e = launch_stage(c->R.N, 32, c->block, c->nshots, &a, c->stream);
+  }
+  if (e != hipSuccess) return c->hipfail(e, "stage kernel launch (recompute)");
+  return DGW_OK;
+}
+
+}  // namespace
+
 extern "C" {
-int dgw_forward_checkpointed(dgw_ctx *c, int64_t, int64_t, const double *, double *) {
+
+int dgw_forward_checkpointed(dgw_ctx *c, int64_t nsteps, int64_t every,
+                             const double *d_obs, double *misfit) {
   if (!c) return DGW_EINVAL;
-  return c->fail(DGW_ESTATE, "adjoint not available in this build");
+  if (!c->have_mesh || !c->have_mat || !c->have_dt)
+    return c->fail(DGW_ESTATE, "mesh, material and dt must be set first");
+  if (nsteps < 1 || every < 1) return c->fail(DGW_EINVAL, "nsteps and ckpt_every must be >= 1");
+  if (!d_obs || !misfit) return c->fail(DGW_EINVAL, "null d_obs or misfit");
+  for (int s = 0; s < c->nshots; ++s) {
+    if (c->h_step[s] != 0)
+      return c->fail(DGW_ESTATE, "every shot must start at step 0 (set its fields first)");
+    const int64_t need = std::min<int64_t>(nsteps, c->h_len[s]);
+    if (c->h_nrec[s] > 0 && c->h_cap_shot[s] < need)
+      return c->fail(DGW_ERANGE, "trace buffer of shot " + std::to_string(s) +
+                                     " is shorter than the run");
+  }
+  c->free_adjoint();
+  c->adj = new dgw_ctx::Adjoint();
+  dgw_ctx::Adjoint *a = c->adj;
+  a->nsteps = nsteps;
+  a->every = every;
+  const size_t n = (size_t)c->nshots * c->mesh.K * 9 * c->R.Np * c->real_size();
+  const size_t per = (size_t)c->mesh.K * 9 * c->R.Np * c->real_size();
+  const int64_t nck = (nsteps + every - 1) / every;
+  for (int64_t i = 0; i < nck; ++i) {
+    void *p = c->dalloc(n);
+    if (!p) {
+      c->free_adjoint();
+      return c->fail(DGW_ENOMEM, "device allocation failed (checkpoints)");
+    }
+    a->ckpt.push_back(p);
+  }
+  int rc;
+  for (int64_t i = 0; i < nck; ++i) {
+    for (int s = 0; s < c->nshots; ++s) {
+      hipError_t e = hipMemcpyAsync((char *)a->ckpt[i] + s * per,
+                                    (const char *)c->d_q[c->loc[s]] + s * per, per,
+                                    hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) return c->hipfail(e, "checkpoint copy");
+    }
+    const int64_t todo = std::min(every, nsteps - i * every);
+    if ((rc = dgw_step(c, todo))) return rc;
+  }
+  // observed data in the device trace layout [S][rmax][3][nsteps]
+  const int R = std::max(c->rmax, 1);
+  std::vector<double> obs((size_t)c->nshots * R * 3 * nsteps, 0.0);
+  int rows = 0;
+  for (int s = 0; s < c->nshots; ++s) rows = std::max(rows, c->h_nrec[s]);
+  for (int s = 0; s < c->nshots; ++s)
+    for (int r = 0; r < c->h_nrec[s]; ++r)
+      for (int cc = 0; cc < 3; ++cc)
+        std::memcpy(&obs[(((size_t)s * R + r) * 3 + cc) * nsteps],
+                    &d_obs[(((size_t)s * rows + r) * 3 + cc) * nsteps],
+                    sizeof(double) * nsteps);
+  a->d_obs = (double *)c->dalloc(sizeof(double) * obs.size());
+  a->d_aux = (int64_t *)c->dalloc(sizeof(int64_t) * c->nshots);
+  if (!a->d_obs || !a->d_aux) return c->fail(DGW_ENOMEM, "device allocation failed");
+  if ((rc = c->upload(a->d_obs, obs.data(), sizeof(double) * obs.size()))) return rc;
+  // misfit per shot from the recorded traces
+  for (int s = 0; s < c->nshots; ++s) {
+    const int nr = c->h_nrec[s];
+    double J = 0.0;
+    if (nr > 0) {
+      const int64_t have = std::min<int64_t>(nsteps, c->h_len[s]);
+      std::vector<double> tr((size_t)nr * 3 * have);
+      int64_t got = 0;
+      if ((rc = dgw_read_traces(c, s, tr.data(), have, &got))) return rc;
+      long double acc = 0;
+      for (int r = 0; r < nr; ++r)
+        for (int cc = 0; cc < 3; ++cc)
+          for (int64_t t = 0; t < have; ++t) {
+            const double d = tr[((size_t)r * 3 + cc) * have + t] -
+                             obs[(((size_t)s * R + r) * 3 + cc) * nsteps + t];
+            acc += (long double)d * d;
+          }
+      J = (double)(0.5L * c->dt * acc);
+    }
+    misfit[s] = J;
+  }
+  a->ready = true;
+  return DGW_OK;
 }
-int dgw_adjoint(dgw_ctx *c, double *, double *, double *) {
+
+int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
   if (!c) return DGW_EINVAL;
-  return c->fail(DGW_ESTATE, "adjoint not available in this build");
+  if (!c->adj || !c->adj->ready)
+    return c->fail(DGW_ESTATE, "call dgw_forward_checkpointed first");
+  if (!g_rho || !g_lam || !g_mu) return c->fail(DGW_EINVAL, "null gradient output");
+  dgw_ctx::Adjoint *a = c->adj;
+  int rc;
+  if ((rc = upload_adjoint_tables(c))) return rc;
+  const int64_t K = c->mesh.K;
+  const int Np = c->R.Np, NF = 4 * c->R.Nfp;
+  const size_t rs = c->real_size();
+  const size_t n = (size_t)c->nshots * K * 9 * Np * rs;
+  std::vector<void *> tmp;
+  auto alloc = [&](size_t bytes) -> void * {
+    void *p = c->dalloc(bytes);
+    if (p) tmp.push_back(p);
+    return p;
+  };
+  auto release = [&]() {
+    for (void *p : tmp) c->dfree(p);
+    tmp.clear();
+  };
+  void *lq = alloc(n), *lr = alloc(n), *res = alloc(n);
+  void *zbuf = alloc((size_t)c->nshots * K * 9 * NF * rs);
+  double *grad = (double *)alloc(sizeof(double) * c->nshots * K * 3);
+  void *st[5] = {nullptr, alloc(n), alloc(n), alloc(n), alloc(n)};
+  std::vector<void *> seg;
+  for (int64_t i = 0; i < a->every; ++i) seg.push_back(alloc(n));
+  bool ok = lq && lr && res && zbuf && grad && st[1] && st[2] && st[3] && st[4];
+  for (void *p : seg) ok = ok && p;
+  if (!ok) {
+    release();
+    return c->fail(DGW_ENOMEM, "device allocation failed (adjoint work space)");
+  }
+  hipError_t e;
+  if ((e = hipMemsetAsync(lq, 0, n, c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(lr, 0, n, c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(res, 0, n, c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(grad, 0, sizeof(double) * c->nshots * K * 3, c->stream)) != hipSuccess) {
+    release();
+    return c->hipfail(e, "hipMemsetAsync");
+  }
+  const int64_t nck = (int64_t)a->ckpt.size();
+  const int64_t stride = K * 9 * Np;
+  for (int64_t ci = nck - 1; ci >= 0 && rc == DGW_OK; --ci) {
+    const int64_t c0 = ci * a->every;
+    const int64_t c1 = std::min(c0 + a->every, a->nsteps);
+    e = hipMemcpyAsync(seg[0], a->ckpt[ci], n, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) { rc = c->hipfail(e, "segment restore"); break; }
+    // recompute the step-start states of the segment
+    for (int64_t s = c0; s + 1 < c1 && rc == DGW_OK; ++s) {
+      if ((e = launch_set_steps(a->d_aux, c->nshots, s, c->stream)) != hipSuccess) {
+        rc = c->hipfail(e, "set_steps");
+        break;
+      }
+      const void *in = seg[s - c0];
+      for (int i = 0; i < 5 && rc == DGW_OK; ++i) {
+        void *out = (i == 4) ? seg[s - c0 + 1] : st[1 + (i & 1)];
+        rc = stage_explicit(c, in, out, res, i);
+        in = out;
+      }
+    }
+    for (int64_t s = c1 - 1; s >= c0 && rc == DGW_OK; --s) {
+      if ((e = launch_set_steps(a->d_aux, c->nshots, s, c->stream)) != hipSuccess) {
+        rc = c->hipfail(e, "set_steps");
+        break;
+      }
+      if (c->rmax > 0 && c->d_trace) {
+        e = launch_inject(c->precision, c->nshots, Np, lq, stride, c->d_nrec,
+                          c->rmax, c->d_rec_elem, c->d_rec_w, c->d_trace, c->cap,
+                          a->d_obs, a->nsteps, a->d_aux, c->d_len, c->dt, c->stream);
+        if (e != hipSuccess) { rc = c->hipfail(e, "inject"); break; }
+      }
+      // stage inputs of step s
+      st[0] = seg[s - c0];
+      for (int i = 0; i < 4 && rc == DGW_OK; ++i) rc = stage_explicit(c, st[i], st[i + 1], res, i);
+      for (int i = 4; i >= 0 && rc == DGW_OK; --i) {
+        if (c->precision == 64) {
+          AdjArgs<double> aa;
+          fill_adj(c, aa, st[i], lq, lr, zbuf, grad, i);
+          e = launch_adjoint_stage(c->R.N, 64, c->nshots, &aa, c->stream);
+        } else {
+          AdjArgs<float> aa;
+          fill_adj(c, aa, st[i], lq, lr, zbuf, grad, i);
+          e = launch_adjoint_stage(c->R.N, 32, c->nshots, &aa, c->stream);
+        }
+        if (e != hipSuccess) rc = c->hipfail(e, "adjoint stage launch");
+      }
+      st[0] = nullptr;
+    }
+  }
+  if (rc == DGW_OK) {
+    std::vector<double> g((size_t)c->nshots * K * 3);
+    rc = c->download(g.data(), grad, sizeof(double) * g.size());
+    if (rc == DGW_OK)
+      for (int s = 0; s < c->nshots; ++s)
+        for (int64_t k = 0; k < K; ++k) {
+          g_rho[(size_t)s * K + k] = g[((size_t)s * K + k) * 3 + 0];
+          g_lam[(size_t)s * K + k] = g[((size_t)s * K + k) * 3 + 1];
+          g_mu[(size_t)s * K + k] = g[((size_t)s * K + k) * 3 + 2];
+        }
+  } else {
+    (void)hipStreamSynchronize(c->stream);
+  }
+  release();
+  return rc;
 }
-int dgw_autotune(dgw_ctx *c, const char *, int *) {
-  if (!c) return DGW_EINVAL;
-  return c->fail(DGW_ESTATE, "autotuner not available in this build");
-}
-}
+
+}  // extern "C"

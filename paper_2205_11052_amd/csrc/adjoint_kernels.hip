@@ -1,0 +1,483 @@
+// HIP kernels of the discrete adjoint: the exact transpose of one fused
+// stage (volume + upwind flux + LIFT) and the parameter gradient
+// (d(L q)/d(rho, lambda, mu))^T w, plus receiver-residual injection.
+//
+// With w the adjoint of a stage's residual (w = lam_r + b lam_q), a reverse
+// stage is   lam_q += dt L^T w,   lam_r = a w,   g += dt (d(Lq)/dm)^T w.
+// It runs as two launches:
+//   adj_lift_kernel: z_f = Fscale_f LIFT_f^T w on every face node (9
+//       components), stored per element and face node;
+//   adj_main_kernel: per face node the transpose of the Riemann flux, taking
+//       the own z for the own side and the neighbour's z (at the matched
+//       node) for the neighbour's flux, which also depends on this
+//       element's trace and impedances; per node the transpose of the
+//       volume operator; the gradient from the explicit 1/rho, lambda, mu
+//       factors and from the impedances of both sides of every face.
+// Notation (own side "-", neighbour "+", n the own outward normal):
+//   [v] = v+ - v-, [t] = (sigma+ - sigma-) n,
+//   kn = (n.[t] + Zp+ n.[v]) / (Zp- + Zp+),
+//   kT = (P_T [t] + Zs+ P_T [v]) / (Zs- + Zs+),  P_T = I - n n^T,
+//   dv = kn n + kT,  dt = Zp- kn n + Zs- kT,
+//   flux = (dt / rho, lambda (n.dv) I + mu (dv n^T + n dv^T)).
+#include <hip/hip_runtime.h>
+
+#include "dgw_internal.h"
+
+namespace dgw {
+
+namespace {
+
+template <int N>
+struct SzA {
+  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Nfp = (N + 1) * (N + 2) / 2;
+};
+
+template <int N>
+struct AdjBlock;
+template <> struct AdjBlock<1> { static constexpr int be = 16; };
+template <> struct AdjBlock<2> { static constexpr int be = 8; };
+template <> struct AdjBlock<3> { static constexpr int be = 6; };
+template <> struct AdjBlock<4> { static constexpr int be = 4; };
+template <> struct AdjBlock<5> { static constexpr int be = 2; };
+template <> struct AdjBlock<6> { static constexpr int be = 2; };
+
+constexpr int kT = 256;
+
+// Adjoint of the face flux for one side.  Inputs: n, jumps as seen from this
+// side, material of this side (ri = 1/rho, la, mu, zp, zs), impedances of the
+// other side (zpo, zso), izp, izs, and z (9 components, Voigt order).
+// Outputs: Jv, Jt (adjoint of the jumps [v] and [t]); dZpm, dZpo, dZsm, dZso
+// (derivatives of z . flux w.r.t. this side's and the other side's
+// impedances); and the forward dv, dt (for the explicit gradient terms).
+template <typename real>
+__device__ inline void flux_adjoint(
+    const real n[3], const real jv[3], const real jt[3], real ri, real la,
+    real mu, real zp, real zs, real zpo, real zso, real izp, real izs,
+    const real z[9], real Jv[3], real Jt[3], real &dZpm, real &dZpo,
+    real &dZsm, real &dZso, real dv[3], real dtr[3]) {
+  const real jvn = jv[0] * n[0] + jv[1] * n[1] + jv[2] * n[2];
+  const real jtn = jt[0] * n[0] + jt[1] * n[1] + jt[2] * n[2];
+  real jvT[3], jtT[3], kTv[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    jvT[a] = jv[a] - jvn * n[a];
+    jtT[a] = jt[a] - jtn * n[a];
+  }
+  const real kn = (jtn + zpo * jvn) * izp;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    kTv[a] = (jtT[a] + zso * jvT[a]) * izs;
+    dv[a] = kn * n[a] + kTv[a];
+    dtr[a] = zp * kn * n[a] + zs * kTv[a];
+  }
+  // a = z_v / rho ; b = lambda tr(z_s) n + mu Zfull n
+  const real trz = z[3] + z[4] + z[5];
+  real av[3], bv[3];
+  av[0] = ri * z[0];
+  av[1] = ri * z[1];
+  av[2] = ri * z[2];
+  bv[0] = la * trz * n[0] + mu * (2 * z[3] * n[0] + z[8] * n[1] + z[7] * n[2]);
+  bv[1] = la * trz * n[1] + mu * (z[8] * n[0] + 2 * z[4] * n[1] + z[6] * n[2]);
+  bv[2] = la * trz * n[2] + mu * (z[7] * n[0] + z[6] * n[1] + 2 * z[5] * n[2]);
+  const real an = av[0] * n[0] + av[1] * n[1] + av[2] * n[2];
+  const real bn = bv[0] * n[0] + bv[1] * n[1] + bv[2] * n[2];
+  const real alpha = bn + zp * an;
+  real beta[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) beta[a] = bv[a] + zs * av[a];
+  const real betan = beta[0] * n[0] + beta[1] * n[1] + beta[2] * n[2];
+  real betaT[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) betaT[a] = beta[a] - betan * n[a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Jt[a] = izp * alpha * n[a] + izs * betaT[a];
+    Jv[a] = zpo * izp * alpha * n[a] + zso * izs * betaT[a];
+  }
+  const real akT = av[0] * kTv[0] + av[1] * kTv[1] + av[2] * kTv[2];
+  const real bkT = betaT[0] * kTv[0] + betaT[1] * kTv[1] + betaT[2] * kTv[2];
+  dZpm = an * kn - alpha * kn * izp;
+  dZpo = alpha * (jvn - kn) * izp;
+  dZsm = akT - izs * bkT;
+  dZso = izs * (betaT[0] * (jvT[0] - kTv[0]) + betaT[1] * (jvT[1] - kTv[1]) +
+                betaT[2] * (jvT[2] - kTv[2]));
+}
+
+template <int N, typename real, int BE>
+__global__ void __launch_bounds__(kT) adj_lift_kernel(AdjArgs<real> A) {
+  constexpr int Np = SzA<N>::Np, Nfp = SzA<N>::Nfp, NF = 4 * Nfp;
+  __shared__ real sw[BE * 9 * Np];
+  __shared__ double sfs[BE * 4];
+  const int shot = blockIdx.y;
+  const int64_t step = A.shot_step[shot];
+  if (step >= A.shot_len[shot]) return;
+  const int64_t k0 = (int64_t)blockIdx.x * BE;
+  if (k0 >= A.K) return;
+  const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
+  const int64_t off = shot * A.shot_stride + k0 * 9 * Np;
+  const real b = (real)A.rk_b;
+  for (int t = threadIdx.x; t < nE * 9 * Np; t += kT)
+    sw[t] = A.lam_r[off + t] + b * A.lam_q[off + t];
+  for (int t = threadIdx.x; t < nE * 4; t += kT)
+    sfs[t] = A.meta[(k0 + t / 4) * DGW_META + M_FSCALE + (t & 3)];
+  __syncthreads();
+  real *zb = A.zbuf + (shot * A.K + k0) * 9 * NF;
+  for (int t = threadIdx.x; t < nE * NF; t += kT) {
+    const int e = t / NF, fm = t - e * NF;
+    const real *we = sw + e * 9 * Np;
+    real acc[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] = 0;
+    for (int i = 0; i < Np; ++i) {
+      const real l = A.LIFT[i * NF + fm];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[c] += l * we[c * Np + i];
+    }
+    const real fs = (real)sfs[e * 4 + fm / Nfp];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) zb[(e * 9 + c) * NF + fm] = fs * acc[c];
+  }
+}
+
+template <int N, typename real, int BE>
+__global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
+  constexpr int Np = SzA<N>::Np, Nfp = SzA<N>::Nfp, NF = 4 * Nfp;
+  __shared__ real sw[BE * 9 * Np];
+  __shared__ real sq[BE * 9 * Np];
+  __shared__ real sfa[BE * 9 * NF];
+  __shared__ double sg[BE * 3 * NF];
+  __shared__ double sgv[BE * 3 * Np];
+  __shared__ double smeta[BE * DGW_META];
+  __shared__ int scn[BE * 4];
+
+  const int shot = blockIdx.y;
+  const int64_t step = A.shot_step[shot];
+  if (step >= A.shot_len[shot]) return;
+  const int64_t k0 = (int64_t)blockIdx.x * BE;
+  if (k0 >= A.K) return;
+  const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
+  const int64_t soff = shot * A.shot_stride;
+  const real *__restrict__ q = A.q + soff;
+  real *lq = A.lam_q + soff;
+  real *lr = A.lam_r + soff;
+  const real *zb = A.zbuf + shot * A.K * 9 * NF;
+  const real b = (real)A.rk_b;
+  const int tid = threadIdx.x;
+
+  for (int t = tid; t < nE * 9 * Np; t += kT) {
+    const int64_t g = k0 * 9 * Np + t;
+    sw[t] = lr[g] + b * lq[g];
+    sq[t] = q[g];
+  }
+  for (int t = tid; t < nE * DGW_META; t += kT) smeta[t] = A.meta[k0 * DGW_META + t];
+  for (int t = tid; t < nE * 4; t += kT) scn[t] = A.conn[k0 * 4 + t];
+  __syncthreads();
+
+  // ---- faces: flux transpose and face gradient terms ------------------
+  for (int t = tid; t < nE * NF; t += kT) {
+    const int e = t / NF, fm = t - e * NF, f = fm / Nfp, m = fm - f * Nfp;
+    const int64_t k = k0 + e;
+    const double *g = smeta + e * DGW_META;
+    const real *qe = sq + e * 9 * Np;
+    const int n1 = A.fmask[fm];
+    real qm[9], qp[9], z[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      qm[c] = qe[c * Np + n1];
+      z[c] = zb[(k * 9 + c) * NF + fm];
+    }
+    const int cn = scn[e * 4 + f];
+    int64_t nb = -1;
+    int f2 = 0, m2 = 0;
+    if (cn >= 0) {
+      nb = cn >> 5;
+      f2 = (cn >> 3) & 3;
+      const int o = cn & 7;
+      const int tab = ((f * 4 + f2) * 6 + o) * Nfp + m;
+      const int n2 = A.nbtab[tab];
+      m2 = A.nbface[tab];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) qp[c] = q[(nb * 9 + c) * Np + n2];
+    } else if (cn == CONN_FREE) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) qp[c] = qm[c];
+#pragma unroll
+      for (int c = 3; c < 9; ++c) qp[c] = -qm[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) qp[c] = 0;
+    }
+    real n[3] = {(real)g[M_NORMAL + 3 * f], (real)g[M_NORMAL + 3 * f + 1],
+                 (real)g[M_NORMAL + 3 * f + 2]};
+    real jv[3], js[6], jt[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) jv[a] = qp[a] - qm[a];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) js[a] = qp[3 + a] - qm[3 + a];
+    jt[0] = js[0] * n[0] + js[5] * n[1] + js[4] * n[2];
+    jt[1] = js[5] * n[0] + js[1] * n[1] + js[3] * n[2];
+    jt[2] = js[4] * n[0] + js[3] * n[1] + js[2] * n[2];
+    const real ri = (real)g[M_RHOINV], la = (real)g[M_LAM], mu = (real)g[M_MU];
+    const real zp = (real)g[M_ZP], zs = (real)g[M_ZS];
+    const real zpo = (real)g[M_ZPNB + f], zso = (real)g[M_ZSNB + f];
+    const real izp = (real)g[M_IZPS + f], izs = (real)g[M_IZSS + f];
+    real Jv[3], Jt[3], dv[3], dtr[3], dZpm, dZpo, dZsm, dZso;
+    flux_adjoint<real>(n, jv, jt, ri, la, mu, zp, zs, zpo, zso, izp, izs, z,
+                       Jv, Jt, dZpm, dZpo, dZsm, dZso, dv, dtr);
+    // adjoint of sigma from [t] = [sigma] n (Voigt xx yy zz yz xz xy)
+    real Js[6];
+    Js[0] = Jt[0] * n[0];
+    Js[1] = Jt[1] * n[1];
+    Js[2] = Jt[2] * n[2];
+    Js[3] = Jt[1] * n[2] + Jt[2] * n[1];
+    Js[4] = Jt[0] * n[2] + Jt[2] * n[0];
+    Js[5] = Jt[0] * n[1] + Jt[1] * n[0];
+    real out[9];
+    if (cn == CONN_FREE) {
+      // v+ = v-, sigma+ = -sigma-
+#pragma unroll
+      for (int a = 0; a < 3; ++a) out[a] = 0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) out[3 + a] = -2 * Js[a];
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) out[a] = -Jv[a];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) out[3 + a] = -Js[a];
+    }
+    // explicit material factors of the own flux
+    const real ndv = n[0] * dv[0] + n[1] * dv[1] + n[2] * dv[2];
+    double gr = -(double)ri * (double)(ri * (z[0] * dtr[0] + z[1] * dtr[1] + z[2] * dtr[2]));
+    double gl = (double)(z[3] + z[4] + z[5]) * (double)ndv;
+    double gm = (double)(2 * (z[3] * dv[0] * n[0] + z[4] * dv[1] * n[1] + z[5] * dv[2] * n[2]) +
+                         z[6] * (dv[1] * n[2] + dv[2] * n[1]) +
+                         z[7] * (dv[0] * n[2] + dv[2] * n[0]) +
+                         z[8] * (dv[0] * n[1] + dv[1] * n[0]));
+    double dzp = dZpm, dzs = dZsm;
+    if (cn < 0) {
+      dzp += dZpo;   // boundary: the ghost impedance is the own impedance
+      dzs += dZso;
+    } else {
+      // the neighbour's flux on this face, seen from the neighbour: normal
+      // -n, jumps -[v] and [t], its own material, this element as "+"
+      const double *gn = A.meta + nb * DGW_META;
+      real zn[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) zn[c] = zb[(nb * 9 + c) * NF + f2 * Nfp + m2];
+      real nn[3] = {-n[0], -n[1], -n[2]};
+      real jvn[3] = {-jv[0], -jv[1], -jv[2]};
+      real Jv2[3], Jt2[3], dv2[3], dt2[3], a1, a2, a3, a4;
+      flux_adjoint<real>(nn, jvn, jt, (real)gn[M_RHOINV], (real)gn[M_LAM],
+                         (real)gn[M_MU], (real)gn[M_ZP], (real)gn[M_ZS], zp, zs,
+                         izp, izs, zn, Jv2, Jt2, a1, a2, a3, a4, dv2, dt2);
+      // this element is the neighbour's "+" side: [v]' = v_k - v_nb etc.
+      out[0] += Jv2[0];
+      out[1] += Jv2[1];
+      out[2] += Jv2[2];
+      out[3] += Jt2[0] * nn[0];
+      out[4] += Jt2[1] * nn[1];
+      out[5] += Jt2[2] * nn[2];
+      out[6] += Jt2[1] * nn[2] + Jt2[2] * nn[1];
+      out[7] += Jt2[0] * nn[2] + Jt2[2] * nn[0];
+      out[8] += Jt2[0] * nn[1] + Jt2[1] * nn[0];
+      dzp += a2;
+      dzs += a4;
+    }
+    real *dst = sfa + e * 9 * NF + fm;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dst[c * NF] = out[c];
+    // impedance chain rule
+    const double rho = g[47], lam = g[M_LAM], muu = g[M_MU];
+    const double Zp = g[M_ZP], Zs = g[M_ZS];
+    gr += dzp * (lam + 2 * muu) / (2 * Zp) + dzs * muu / (2 * Zs);
+    gl += dzp * rho / (2 * Zp);
+    gm += dzp * rho / Zp + dzs * rho / (2 * Zs);
+    sg[(e * 3 + 0) * NF + fm] = gr;
+    sg[(e * 3 + 1) * NF + fm] = gl;
+    sg[(e * 3 + 2) * NF + fm] = gm;
+  }
+  __syncthreads();
+
+  // ---- nodes: volume transpose, update, volume gradient terms --------
+  for (int t = tid; t < nE * Np; t += kT) {
+    const int e = t / Np, i = t - e * Np;
+    const int64_t k = k0 + e;
+    const double *g = smeta + e * DGW_META;
+    const real *we = sw + e * 9 * Np;
+    const real *qe = sq + e * 9 * Np;
+    real fr[9], fs[9], ft[9];   // forward D_r q
+    real ar[9], as[9], at[9];   // transposed D_r^T w
+#pragma unroll
+    for (int c = 0; c < 9; ++c) fr[c] = fs[c] = ft[c] = ar[c] = as[c] = at[c] = 0;
+    for (int j = 0; j < Np; ++j) {
+      const real f0 = A.DrT[j * Np + i], f1 = A.DsT[j * Np + i], f2 = A.DtT[j * Np + i];
+      const real b0 = A.Dr[j * Np + i], b1 = A.Ds[j * Np + i], b2 = A.Dt[j * Np + i];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        const real v = qe[c * Np + j], u = we[c * Np + j];
+        fr[c] += f0 * v;
+        fs[c] += f1 * v;
+        ft[c] += f2 * v;
+        ar[c] += b0 * u;
+        as[c] += b1 * u;
+        at[c] += b2 * u;
+      }
+    }
+    real X[9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) X[u] = (real)g[M_XINV + u];
+    auto Dq = [&](int c, int bb) -> real {
+      return X[bb] * fr[c] + X[3 + bb] * fs[c] + X[6 + bb] * ft[c];
+    };
+    auto DTw = [&](int c, int bb) -> real {
+      return X[bb] * ar[c] + X[3 + bb] * as[c] + X[6 + bb] * at[c];
+    };
+    const real ri = (real)g[M_RHOINV], la = (real)g[M_LAM], mu = (real)g[M_MU];
+    real adj[9];
+    // velocity: sum_b d_b^T T_ab, T_aa = la tr(w_s) + 2 mu w_aa, T_ab = mu w_ab
+    adj[0] = la * (DTw(3, 0) + DTw(4, 0) + DTw(5, 0)) + 2 * mu * DTw(3, 0) +
+             mu * (DTw(8, 1) + DTw(7, 2));
+    adj[1] = la * (DTw(3, 1) + DTw(4, 1) + DTw(5, 1)) + 2 * mu * DTw(4, 1) +
+             mu * (DTw(8, 0) + DTw(6, 2));
+    adj[2] = la * (DTw(3, 2) + DTw(4, 2) + DTw(5, 2)) + 2 * mu * DTw(5, 2) +
+             mu * (DTw(7, 0) + DTw(6, 1));
+    // stress: (1/rho) d^T of the velocity adjoints
+    adj[3] = ri * DTw(0, 0);
+    adj[4] = ri * DTw(1, 1);
+    adj[5] = ri * DTw(2, 2);
+    adj[6] = ri * (DTw(1, 2) + DTw(2, 1));
+    adj[7] = ri * (DTw(0, 2) + DTw(2, 0));
+    adj[8] = ri * (DTw(0, 1) + DTw(1, 0));
+    const real *fa = sfa + e * 9 * NF;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int mm = A.facepos[f * Np + i];
+      if (mm >= 0) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) adj[c] += fa[c * NF + f * Nfp + mm];
+      }
+    }
+    const real rdt = (real)A.dt, ra = (real)A.rk_a;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const int64_t idx = (k * 9 + c) * Np + i;
+      lq[idx] += rdt * adj[c];
+      lr[idx] = ra * we[c * Np + i];
+    }
+    // volume gradient terms at this node
+    const real divv = Dq(0, 0) + Dq(1, 1) + Dq(2, 2);
+    const real ds0 = Dq(3, 0) + Dq(8, 1) + Dq(7, 2);
+    const real ds1 = Dq(8, 0) + Dq(4, 1) + Dq(6, 2);
+    const real ds2 = Dq(7, 0) + Dq(6, 1) + Dq(5, 2);
+    const double w0 = we[0 * Np + i], w1 = we[1 * Np + i], w2 = we[2 * Np + i];
+    const double w3 = we[3 * Np + i], w4 = we[4 * Np + i], w5 = we[5 * Np + i];
+    const double w6 = we[6 * Np + i], w7 = we[7 * Np + i], w8 = we[8 * Np + i];
+    const double rinv = g[M_RHOINV];
+    sgv[(e * 3 + 0) * Np + i] = -rinv * rinv * (w0 * ds0 + w1 * ds1 + w2 * ds2);
+    sgv[(e * 3 + 1) * Np + i] = (w3 + w4 + w5) * (double)divv;
+    sgv[(e * 3 + 2) * Np + i] =
+        2.0 * (w3 * Dq(0, 0) + w4 * Dq(1, 1) + w5 * Dq(2, 2)) +
+        w6 * (double)(Dq(1, 2) + Dq(2, 1)) + w7 * (double)(Dq(0, 2) + Dq(2, 0)) +
+        w8 * (double)(Dq(0, 1) + Dq(1, 0));
+  }
+  __syncthreads();
+  // ---- per-element gradient reduction (FP64) --------------------------
+  for (int t = tid; t < nE * 3; t += kT) {
+    const int e = t / 3, p = t - 3 * e;
+    double s = 0.0;
+    for (int u = 0; u < NF; ++u) s += sg[(e * 3 + p) * NF + u];
+    for (int u = 0; u < Np; ++u) s += sgv[(e * 3 + p) * Np + u];
+    A.grad[(shot * A.K + k0 + e) * 3 + p] += A.dt * s;
+  }
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256)
+inject_kernel(int Np, real *lam_q, int64_t shot_stride, const int32_t *nrec,
+              int rmax, const int32_t *rec_elem, const double *rec_w,
+              const double *trace, int64_t cap, const double *d_obs,
+              int64_t nobs, const int64_t *shot_step, const int64_t *shot_len,
+              double dt) {
+  const int shot = blockIdx.x;
+  const int64_t step = shot_step[shot];
+  if (step >= shot_len[shot] || step >= cap || step >= nobs) return;
+  const int nr = nrec[shot];
+  real *lq = lam_q + shot * shot_stride;
+  // thread (c, j) owns lam_q[k][c][j] of every receiver element: the
+  // receivers are visited in order, so shared elements never race
+  for (int t = threadIdx.x; t < 3 * Np; t += blockDim.x) {
+    const int c = t / Np, j = t - c * Np;
+    for (int r = 0; r < nr; ++r) {
+      const int64_t base = ((int64_t)shot * rmax + r) * 3 + c;
+      const double res = trace[base * cap + step] - d_obs[base * nobs + step];
+      const int64_t k = rec_elem[(int64_t)shot * rmax + r];
+      const double add = dt * rec_w[((int64_t)shot * rmax + r) * Np + j] * res;
+      lq[(k * 9 + c) * Np + j] += (real)add;
+    }
+  }
+}
+
+__global__ void set_steps_kernel(int64_t *steps, int n, int64_t value) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) steps[i] = value;
+}
+
+template <int N, typename real>
+hipError_t adj_launch_t(int nshots, const AdjArgs<real> &a, hipStream_t st) {
+  constexpr int BE = AdjBlock<N>::be;
+  dim3 grid((unsigned)((a.K + BE - 1) / BE), (unsigned)nshots);
+  hipLaunchKernelGGL((adj_lift_kernel<N, real, BE>), grid, dim3(kT), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((adj_main_kernel<N, real, BE>), grid, dim3(kT), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t adj_launch_r(int N, int nshots, const void *args, hipStream_t st) {
+  const AdjArgs<real> &a = *(const AdjArgs<real> *)args;
+  switch (N) {
+    case 1: return adj_launch_t<1, real>(nshots, a, st);
+    case 2: return adj_launch_t<2, real>(nshots, a, st);
+    case 3: return adj_launch_t<3, real>(nshots, a, st);
+    case 4: return adj_launch_t<4, real>(nshots, a, st);
+    case 5: return adj_launch_t<5, real>(nshots, a, st);
+    case 6: return adj_launch_t<6, real>(nshots, a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_stage(int N, int precision, int nshots,
+                                const void *args, hipStream_t st) {
+  if (precision == 64) return adj_launch_r<double>(N, nshots, args, st);
+  return adj_launch_r<float>(N, nshots, args, st);
+}
+
+hipError_t launch_inject(int precision, int nshots, int Np, void *lam_q,
+                         int64_t shot_stride, const int32_t *nrec, int rmax,
+                         const int32_t *rec_elem, const double *rec_w,
+                         const double *trace, int64_t cap, const double *d_obs,
+                         int64_t nobs, const int64_t *shot_step,
+                         const int64_t *shot_len, double dt, hipStream_t st) {
+  if (precision == 64)
+    hipLaunchKernelGGL(inject_kernel<double>, dim3(nshots), dim3(256), 0, st, Np,
+                       (double *)lam_q, shot_stride, nrec, rmax, rec_elem, rec_w,
+                       trace, cap, d_obs, nobs, shot_step, shot_len, dt);
+  else
+    hipLaunchKernelGGL(inject_kernel<float>, dim3(nshots), dim3(256), 0, st, Np,
+                       (float *)lam_q, shot_stride, nrec, rmax, rec_elem, rec_w,
+                       trace, cap, d_obs, nobs, shot_step, shot_len, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_steps(int64_t *steps, int nshots, int64_t value,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(set_steps_kernel, dim3((nshots + 255) / 256), dim3(256), 0,
+                     st, steps, nshots, value);
+  return hipGetLastError();
+}
+
+}  // namespace dgw

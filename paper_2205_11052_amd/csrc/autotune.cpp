@@ -1,0 +1,163 @@
+// Launch-shape autotuner of the stage kernel.
+//
+// Every implemented launch shape (elements per work-group x work-groups per
+// compute unit of the persistent grid) is timed with HIP events on the
+// context's stream over real stage launches of the context's own workload,
+// writing into scratch buffers so the solver state is untouched.  The fastest
+// shape is kept; with a cache path the choice is stored in a flat JSON object
+// keyed by order, precision, element count and shot count, and read back on
+// later calls instead of timing again.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+
+#include "../../include/dgw.h"
+#include "dgw_ctx.h"
+
+using namespace dgw;
+
+namespace {
+
+std::map<std::string, long> read_cache(const char *path) {
+  std::map<std::string, long> out;
+  std::ifstream f(path);
+  if (!f) return out;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  size_t p = 0;
+  while ((p = s.find('"', p)) != std::string::npos) {
+    const size_t q = s.find('"', p + 1);
+    if (q == std::string::npos) break;
+    const std::string key = s.substr(p + 1, q - p - 1);
+    size_t colon = s.find(':', q);
+    if (colon == std::string::npos) break;
+    long v = 0;
+    if (std::sscanf(s.c_str() + colon + 1, " %ld", &v) == 1) out[key] = v;
+    p = colon + 1;
+  }
+  return out;
+}
+
+bool write_cache(const char *path, const std::map<std::string, long> &m) {
+  std::ofstream f(path);
+  if (!f) return false;
+  f << "{";
+  bool first = true;
+  for (const auto &kv : m) {
+    f << (first ? "" : ",") << "\n  \"" << kv.first << "\": " << kv.second;
+    first = false;
+  }
+  f << "\n}\n";
+  return (bool)f;
+}
+
+template <typename real>
+void fill(dgw_ctx *c, StageArgs<real> &a, void *out, void *res) {
+  a.q_in = (const real *)c->d_q[c->cur];
+  a.q_out = (real *)out;
+  a.res = (real *)res;
+  a.meta = c->d_meta;
+  a.conn = c->d_conn;
+  a.nbtab = c->d_nbtab;
+  a.DrT = (const real *)c->d_DrT;
+  a.DsT = (const real *)c->d_DsT;
+  a.DtT = (const real *)c->d_DtT;
+  a.LIFTT = (const real *)c->d_LIFTT;
+  a.fmask = c->d_fmask;
+  a.K = c->mesh.K;
+  a.shot_stride = c->mesh.K * 9 * c->R.Np;
+  a.shot_step = c->d_step;
+  a.shot_len = c->d_len;
+  a.src_elem = c->d_src_elem;
+  a.src_vec = c->d_src_vec;
+  a.src_par = c->d_src_par;
+  a.rk_a = rk_a()[1];
+  a.rk_b = rk_b()[1];
+  a.rk_c = rk_c()[1];
+  a.dt = c->dt;
+}
+
+}  // namespace
+
+extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *choice) {
+  if (!c) return DGW_EINVAL;
+  if (!c->have_mesh || !c->have_mat || !c->have_dt)
+    return c->fail(DGW_ESTATE, "mesh, material and dt must be set first");
+  char key[128];
+  std::snprintf(key, sizeof key, "N%d_fp%d_K%lld_S%d", c->R.N, c->precision,
+                (long long)c->mesh.K, c->nshots);
+  const std::vector<int> opts = stage_block_choices(c->R.N, c->precision);
+  std::map<std::string, long> cache;
+  if (cache_path) {
+    cache = read_cache(cache_path);
+    auto it = cache.find(key);
+    if (it != cache.end())
+      for (int o : opts)
+        if (o == it->second) {
+          int rc = dgw_set_block(c, o);
+          if (choice) *choice = o;
+          return rc;
+        }
+  }
+  const size_t n = (size_t)c->nshots * c->mesh.K * 9 * c->R.Np * c->real_size();
+  void *out = c->dalloc(n), *res = c->dalloc(n);
+  if (!out || !res) {
+    c->dfree(out);
+    c->dfree(res);
+    return c->fail(DGW_ENOMEM, "device allocation failed (autotune scratch)");
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  int best = opts[0];
+  float best_ms = 1e30f;
+  int rc = DGW_OK;
+  for (int o : opts) {
+    hipError_t err = hipSuccess;
+    const int reps = 10;
+    for (int r = 0; r < reps + 2 && err == hipSuccess; ++r) {
+      if (r == 2) (void)hipEventRecord(e0, c->stream);
+      if (c->precision == 64) {
+        StageArgs<double> a;
+        fill(c, a, out, res);
+        err = launch_stage(c->R.N, 64, o, c->nshots, &a, c->stream);
+      } else {
+        StageArgs<float> a;
+        fill(c, a, out, res);
+        err = launch_stage(c->R.N, 32, o, c->nshots, &a, c->stream);
+      }
+    }
+    if (err != hipSuccess) {
+      rc = c->hipfail(err, "autotune launch");
+      break;
+    }
+    (void)hipEventRecord(e1, c->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= reps;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = o;
+    }
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->dfree(out);
+  c->dfree(res);
+  if (rc) return rc;
+  if ((rc = dgw_set_block(c, best))) return rc;
+  if (choice) *choice = best;
+  if (cache_path) {
+    cache[key] = best;
+    if (!write_cache(cache_path, cache))
+      return c->fail(DGW_EINVAL, std::string("cannot write ") + cache_path);
+  }
+  return DGW_OK;
+}

@@ -50,6 +50,7 @@ struct MeshData {
   std::vector<double> geo;       // [K][DGW_META] geometry part filled
   std::vector<int32_t> conn;     // [K][4]
   std::vector<int32_t> nbtab;    // [4][4][6][Nfp] neighbour volume node
+  std::vector<int32_t> nbface;   // [4][4][6][Nfp] neighbour face-local node
   std::vector<double> volume;    // [K]
   std::vector<double> area;      // [K][4]
 };
@@ -98,9 +99,47 @@ struct RecArgs {
   const int64_t *shot_len;
 };
 
+// Reverse (adjoint) stage.  w = lam_r + b lam_q is the adjoint of the stage's
+// residual; lam_q += dt L^T w, lam_r = a w, grad += dt (d(L q)/dm)^T w.
+template <typename real>
+struct AdjArgs {
+  const real *q;                // stage input state
+  real *lam_q, *lam_r;          // adjoint of q and of res
+  real *zbuf;                   // [S][K][9][4 Nfp] Fscale LIFT^T w
+  double *grad;                 // [S][K][3] (rho, lambda, mu)
+  const double *meta;
+  const int32_t *conn;
+  const int32_t *nbtab, *nbface;
+  const real *DrT, *DsT, *DtT;  // [j][i] = D(i, j)
+  const real *Dr, *Ds, *Dt;     // [j][i] = D(j, i)
+  const real *LIFT;             // [Np][4 Nfp]
+  const int32_t *fmask;         // [4 Nfp]
+  const int32_t *facepos;       // [4][Np]: face-local index or -1
+  int64_t K;
+  int64_t shot_stride;
+  const int64_t *shot_step;
+  const int64_t *shot_len;
+  double rk_a, rk_b, dt;
+};
+
+// Launchers (adjoint_kernels.hip).
+hipError_t launch_adjoint_stage(int N, int precision, int nshots,
+                                const void *args, hipStream_t st);
+// lam_q[k_r][c][j] += dt w_r[j] (trace[r][c][step] - d_obs[r][c][step])
+hipError_t launch_inject(int precision, int nshots, int Np, void *lam_q,
+                         int64_t shot_stride, const int32_t *nrec, int rmax,
+                         const int32_t *rec_elem, const double *rec_w,
+                         const double *trace, int64_t cap, const double *d_obs,
+                         int64_t nobs, const int64_t *shot_step,
+                         const int64_t *shot_len, double dt, hipStream_t st);
+hipError_t launch_set_steps(int64_t *steps, int nshots, int64_t value,
+                            hipStream_t st);
+
 // Launchers (kernels.hip); return the launch error.
 hipError_t launch_stage(int N, int precision, int be, int nshots,
                         const void *args, hipStream_t st);
+hipError_t launch_copy(int precision, void *dst, const void *src, int64_t n,
+                       hipStream_t st);
 hipError_t launch_receivers(int precision, int nshots, const RecArgs &a,
                             hipStream_t st);
 hipError_t launch_energy(int precision, const void *q, int64_t K, int Np,

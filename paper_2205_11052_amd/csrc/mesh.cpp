@@ -160,6 +160,7 @@ std::string build_mesh(const RefElem &R, int64_t nvert, const double *vxyz,
     lat[(R.bary[4 * n + 1] * (N + 1) + R.bary[4 * n + 2]) * (N + 1) +
         R.bary[4 * n + 3]] = n;
   m.nbtab.assign(4 * 4 * 6 * Nfp, -1);
+  m.nbface.assign(4 * 4 * 6 * Nfp, -1);
   for (int f = 0; f < 4; ++f)
     for (int f2 = 0; f2 < 4; ++f2)
       for (int o = 0; o < 6; ++o)
@@ -172,6 +173,9 @@ std::string build_mesh(const RefElem &R, int64_t nvert, const double *vxyz,
           for (int u = 0; u < 3; ++u) B[lb[kPerm[o][u]]] = R.bary[4 * n + la[u]];
           int idx = lat[(B[1] * (N + 1) + B[2]) * (N + 1) + B[3]];
           m.nbtab[((f * 4 + f2) * 6 + o) * Nfp + mm] = idx;
+          for (int q = 0; q < Nfp; ++q)
+            if (R.fmask[f2 * Nfp + q] == idx)
+              m.nbface[((f * 4 + f2) * 6 + o) * Nfp + mm] = q;
         }
   return "";
 }

@@ -1,0 +1,170 @@
+"""GPU discrete adjoint: gradient parity with the oracle's reverse-mode
+gradient, central finite differences of the GPU forward, FP32 vs FP64, the
+torch.autograd.Function wrapper, and per-shot gradients of a batch.
+
+Observed data are produced by the oracle (never by the GPU path)."""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_helpers import gpu_solver, oracle_problem, rel_l2, say
+from oracle import adjoint as OA
+from oracle import solver as O
+from paper_2205_11052_amd import ElasticMisfit
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float64))
+
+
+def _random_medium(K, seed):
+    rng = np.random.default_rng(seed)
+    cp = rng.uniform(1.5, 3.0, K)
+    cs = cp / rng.uniform(1.5, 2.2, K)
+    rho = rng.uniform(1.0, 3.0, K)
+    return W.lame_from_velocities(cp, cs, rho)
+
+
+def _small_case(N, periodic=False, nsteps=24, seed=0):
+    n = 3 if periodic else 2
+    mesh = W.kuhn_cube(n, 1.0, periodic=periodic)
+    K = mesh["etov"].shape[0]
+    true = _random_medium(K, 40 + seed)
+    start = [m * (1 + 0.05 * np.sin(np.arange(K) + i)) for i, m in enumerate(true)]
+    P = oracle_problem(mesh, N)
+    dt = P.suggest_dt(*true, 0.5)
+    src, f0, t0 = np.array([0.41, 0.47, 0.53]), 4.0, 0.05
+    rec = np.array([[0.2, 0.3, 1.0], [0.8, 0.6, 0.7], [0.1, 0.9, 0.0],
+                    [0.55, 0.45, 0.95]])
+    P.set_source(src, f0, t0)
+    P.set_receivers(rec)
+    q0 = torch.zeros(K, 9, P.Np, dtype=torch.float64)
+    with torch.no_grad():
+        _, d_obs = O.run(P, q0, *(_t(a) for a in true), dt, nsteps, record=True)
+    return dict(mesh=mesh, K=K, N=N, P=P, dt=dt, src=src, f0=f0, t0=t0,
+                rec=rec, start=start, d_obs=d_obs.numpy(), nsteps=nsteps, q0=q0)
+
+
+def _gpu(case, precision=64, nshots=1):
+    s = gpu_solver(case["mesh"], case["N"], *case["start"], case["dt"],
+                   precision, nshots)
+    for i in range(nshots):
+        s.set_source(i, case["src"], case["f0"], case["t0"])
+        s.set_receivers(i, case["rec"], case["nsteps"])
+    return s
+
+
+@pytest.mark.parametrize("N,periodic", [(1, False), (2, False), (3, False),
+                                        (4, False), (2, True)])
+def test_gpu_gradient_equals_oracle_adjoint(N, periodic):
+    case = _small_case(N, periodic)
+    say("case adjoint parity N=%d periodic=%s K=%d" % (N, periodic, case["K"]))
+    J_o, gr, gl, gm = OA.misfit_gradient(
+        case["P"], *(_t(a) for a in case["start"]), case["q0"], case["dt"],
+        case["nsteps"], _t(case["d_obs"]), ckpt_every=7)
+    s = _gpu(case)
+    s.zero_fields()
+    mis = s.forward_checkpointed(case["nsteps"], 7, case["d_obs"][None])
+    g = s.adjoint()
+    assert abs(mis[0] - J_o.item()) <= 1e-12 * J_o.item()
+    errs = [rel_l2(g[i][0], ref.numpy()) for i, ref in enumerate((gr, gl, gm))]
+    say("N=%d misfit %.6e grad rel err rho %.2e lam %.2e mu %.2e"
+        % (N, mis[0], *errs))
+    assert max(errs) <= 1e-10
+
+
+def test_fp32_gradient_close_to_fp64():
+    case = _small_case(3, nsteps=30, seed=3)
+    say("case adjoint fp32 vs fp64")
+    out = []
+    for prec in (64, 32):
+        s = _gpu(case, prec)
+        s.zero_fields()
+        s.forward_checkpointed(case["nsteps"], 10, case["d_obs"][None])
+        out.append(s.adjoint())
+    errs = [rel_l2(out[1][i], out[0][i]) for i in range(3)]
+    say("fp32 gradient rel err vs fp64: %.2e %.2e %.2e" % tuple(errs))
+    assert max(errs) <= 1e-3
+
+
+def test_autograd_function_and_batched_shots():
+    case = _small_case(2, nsteps=20, seed=5)
+    say("case autograd + batched gradients")
+    s = _gpu(case, 64, nshots=2)
+    # second shot: a different source position
+    s.set_source(1, np.array([0.6, 0.3, 0.4]), case["f0"], case["t0"])
+    d2 = np.stack([case["d_obs"], 0.5 * case["d_obs"]])
+    rho, lam, mu = (torch.tensor(a, requires_grad=True) for a in case["start"])
+    mis = ElasticMisfit.apply(rho, lam, mu, s, d2, case["nsteps"], 5)
+    total = mis.sum()
+    total.backward()
+    g_all = s.adjoint()
+    for p, gi in zip((rho, lam, mu), g_all):
+        assert np.allclose(p.grad.numpy(), gi.sum(axis=0), rtol=1e-12, atol=0)
+    # each shot of the batch equals a single-shot run of that shot
+    for i, pos in enumerate((case["src"], np.array([0.6, 0.3, 0.4]))):
+        one = _gpu(case, 64, 1)
+        one.set_source(0, pos, case["f0"], case["t0"])
+        one.zero_fields()
+        m1 = one.forward_checkpointed(case["nsteps"], 5, d2[i][None])
+        g1 = one.adjoint()
+        assert abs(m1[0] - mis[i].item()) <= 1e-14 * m1[0]
+        for a, b in zip(g1, g_all):
+            assert np.array_equal(a[0], b[i])
+
+
+def _c3_reduced(n=4, nsteps=300):
+    """Layered true medium, blob-perturbed start, 64 surface receivers."""
+    wt = W.build_workload("c3_adjoint", n=n)
+    ws = W.build_workload("c3_adjoint", n=n, medium="blob")
+    P = oracle_problem(wt["mesh"], wt["N"])
+    dt = P.suggest_dt(wt["rho"], wt["lam"], wt["mu"], wt["cfl"])
+    P.set_source(wt["source"], wt["f0"], wt["t0"], wt["amp"])
+    P.set_receivers(wt["receivers"])
+    q0 = torch.zeros(wt["K"], 9, P.Np, dtype=torch.float64)
+    with torch.no_grad():
+        _, d = O.run(P, q0, _t(wt["rho"]), _t(wt["lam"]), _t(wt["mu"]), dt,
+                     nsteps, record=True)
+    return wt, ws, dt, d.numpy()
+
+
+def test_gradient_matches_central_differences():
+    """Reduced gradient configuration (6*4^3 elements, order 3, 300 steps):
+    GPU FP64 adjoint vs central differences of the GPU forward on 20 seeded
+    elements (step 1e-6 relative), relative error <= 1e-4."""
+    nsteps = 300
+    wt, ws, dt, d = _c3_reduced(4, nsteps)
+    say("case FD check K=%d steps=%d" % (wt["K"], nsteps))
+    s = gpu_solver(ws["mesh"], ws["N"], ws["rho"], ws["lam"], ws["mu"], dt)
+    s.set_source(0, ws["source"], ws["f0"], ws["t0"], ws["amp"])
+    s.set_receivers(0, ws["receivers"], nsteps)
+    s.zero_fields()
+    s.forward_checkpointed(nsteps, 100, d[None])
+    g = [x[0] for x in s.adjoint()]
+    gmax = max(np.abs(x).max() for x in g)
+    eligible = np.nonzero(np.maximum.reduce([np.abs(x) for x in g]) >= 1e-3 * gmax)[0]
+    rng = np.random.default_rng(52)
+    elems = rng.choice(eligible, size=min(20, len(eligible)), replace=False)
+    base = [np.array(ws["rho"]), np.array(ws["lam"]), np.array(ws["mu"])]
+    worst = 0.0
+    for k in elems:
+        for p in range(3):
+            if abs(g[p][k]) < 1e-3 * gmax:
+                continue
+            delta = 1e-6 * base[p][k]
+            vals = []
+            for sgn in (1, -1):
+                m = [b.copy() for b in base]
+                m[p][k] += sgn * delta
+                s.set_material(*m)
+                s.zero_fields()
+                vals.append(s.forward_checkpointed(nsteps, nsteps, d[None])[0])
+            fd = (vals[0] - vals[1]) / (2 * delta)
+            worst = max(worst, abs(fd - g[p][k]) / abs(fd))
+    s.set_material(*base)
+    say("FD worst relative error %.2e over %d elements" % (worst, len(elems)))
+    assert worst <= 1e-4
