@@ -58,6 +58,9 @@ def build_solver(w, precision, nshots=1, stream=None, shots=None):
         n = 0 if shots is None else int(shots[1][i])
         s.set_source(i, pos, w["f0"], w["t0"], w["amp"], nsteps=n)
         s.set_receivers(i, w["receivers"], 4096)
+    # launch shape (elements per work-group, persistent grid) chosen by the
+    # library's autotuner on this very workload
+    s.shape = s.autotune()
     return s
 
 
@@ -132,10 +135,12 @@ def main():
     with torch.cuda.stream(stream):
         s = build_solver(w, 64, stream=stream.cuda_stream)
         if args.block:
-            s.set_block(args.block)
+            s.set_launch(args.block, 0)
+            s.shape = (args.block, 0)
         sec, wall = timed_steps(torch, s, stream, args.steps, args.warmup)
         kms, nl = kernel_avg_ms(s)
         s.check_finite()
+        shape64 = s.shape
     value = dof * 5 * args.steps / sec / 1e9
     bytes_launch = stage_bytes(K, Np, 8)
     achieved = bytes_launch / (kms / 1e3) / 1e9
@@ -155,7 +160,9 @@ def main():
                      "kernel": "stage_kernel<4,double>",
                      "kernel_avg_ms": round(kms, 5),
                      "launches_timed": nl,
-                     "bytes_per_launch": bytes_launch},
+                     "bytes_per_launch": bytes_launch,
+                     "launch_shape": {"elements_per_workgroup": shape64[0],
+                                      "persistent_wgs_per_cu": shape64[1]}},
     }
     del s
     if not args.no_forms:
@@ -164,6 +171,7 @@ def main():
             s32 = build_solver(w, 32, stream=stream.cuda_stream)
             sec32, _ = timed_steps(torch, s32, stream, args.steps, args.warmup)
             k32, _ = kernel_avg_ms(s32)
+            shape32 = s32.shape
         del s32
         forms["fp32"] = {
             "value": round(dof * 5 * args.steps / sec32 / 1e9, 3),
@@ -171,7 +179,8 @@ def main():
             "speedup_vs_fp64": round(sec / sec32, 3),
             "kernel_avg_ms": round(k32, 5),
             "hbm_frac": round(stage_bytes(K, Np, 4) / (k32 / 1e3) / 1e9
-                              / HBM_PEAK_GBS, 4)}
+                              / HBM_PEAK_GBS, 4),
+            "launch_shape": list(shape32)}
         pos, lens = W.batched_shots()
         nb = len(pos)
         bsteps = max(10, args.steps // 10)
@@ -179,13 +188,21 @@ def main():
             sb = build_solver(w, 32, nshots=nb, stream=stream.cuda_stream,
                               shots=(pos, lens))
             secb, _ = timed_steps(torch, sb, stream, bsteps, 2)
+            kb, _ = kernel_avg_ms(sb, 2)
+            shapeb = sb.shape
         del sb
         forms["fp32_batched_32_shots"] = {
             "value": round(nb * dof * 5 * bsteps / secb / 1e9, 3),
             "ms_per_step": round(secb / bsteps * 1e3, 4),
             "steps": bsteps,
             "speedup_vs_fp64": round((nb * bsteps / secb)
-                                     / (args.steps / sec), 3)}
+                                     / (args.steps / sec), 3),
+            "kernel_avg_ms": round(kb, 5),
+            "hbm_frac": round(stage_bytes(K, Np, 4, nb) / (kb / 1e3) / 1e9
+                              / HBM_PEAK_GBS, 4),
+            "launch_shape": list(shapeb),
+            "note": "32 shots, one launch per stage over all shots, graph "
+                    "replay; lengths 500-2000 steps, all active in the window"}
         out["forms"] = forms
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)

@@ -175,14 +175,21 @@ int dgw_forward_checkpointed(dgw_ctx *ctx, int64_t nsteps, int64_t ckpt_every,
 int dgw_adjoint(dgw_ctx *ctx, double *g_rho, double *g_lam, double *g_mu);
 
 /* Time the available launch shapes of the stage kernel on this context's
- * workload and keep the fastest; if cache_path is not NULL the choice is read
+ * workload (real stage launches into scratch buffers; the solver state is not
+ * changed) and keep the fastest; if cache_path is not NULL the choice is read
  * from / written to that JSON file (keyed by order, precision, element count
- * and shot count).  *choice receives the chosen elements-per-block value. */
-int dgw_autotune(dgw_ctx *ctx, const char *cache_path, int *choice);
+ * and shot count).  The chosen shape is returned through the two pointers
+ * (either may be NULL); see dgw_set_launch. */
+int dgw_autotune(dgw_ctx *ctx, const char *cache_path, int *elems_per_block,
+                 int *wgs_per_cu);
 
-/* Launch shape of the stage kernel: elements per work-group (0 = default).
- * DGW_EINVAL for values the kernel does not implement. */
-int dgw_set_block(dgw_ctx *ctx, int elems_per_block);
+/* Launch shape of the stage kernel: elements per work-group (0 = default;
+ * DGW_EINVAL for values the kernel does not implement) and work-groups per
+ * compute unit of a persistent grid (0 = one work-group per block of
+ * elements, the default; 1..64 = a persistent grid of that many work-groups
+ * per CU, rounded up to a multiple of 8, looping over the blocks of all
+ * shots). */
+int dgw_set_launch(dgw_ctx *ctx, int elems_per_block, int wgs_per_cu);
 
 /* Average duration in milliseconds of the stage-kernel launches made by the
  * last dgw_step call, measured with HIP events on the context's stream

@@ -79,6 +79,11 @@ int dgw_ctx::ensure_device() {
   int n = 0;
   hipError_t e = hipGetDeviceCount(&n);
   if (e != hipSuccess || n <= 0) return fail(DGW_EHIP, "no HIP device available");
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      cus > 0)
+    ncu = cus;
   if (!stream) {
     e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
     if (e != hipSuccess) return hipfail(e, "hipStreamCreate");
@@ -334,11 +339,11 @@ int dgw_ctx::enqueue_step(int from, bool timed) {
     if (precision == 64) {
       StageArgs<double> a;
       fill_stage_args(this, a, i, from);
-      e = launch_stage(R.N, 64, block, nshots, &a, stream);
+      e = launch_stage(R.N, 64, block, wpc, ncu, nshots, &a, stream);
     } else {
       StageArgs<float> a;
       fill_stage_args(this, a, i, from);
-      e = launch_stage(R.N, 32, block, nshots, &a, stream);
+      e = launch_stage(R.N, 32, block, wpc, ncu, nshots, &a, stream);
     }
     if (e != hipSuccess) return hipfail(e, "stage kernel launch");
     if (timed && ev_pool_used + 2 <= (int)ev_pool.size()) {
@@ -794,13 +799,16 @@ int dgw_ref_operators(int order, double *Dr, double *Ds, double *Dt, double *M,
   return DGW_OK;
 }
 
-int dgw_set_block(dgw_ctx *c, int elems_per_block) {
+int dgw_set_launch(dgw_ctx *c, int elems_per_block, int wgs_per_cu) {
   if (!c) return DGW_EINVAL;
   std::vector<int> ch = stage_block_choices(c->R.N, c->precision);
   if (elems_per_block == 0) elems_per_block = ch[0];
   if (std::find(ch.begin(), ch.end(), elems_per_block) == ch.end())
     return c->fail(DGW_EINVAL, "unsupported elements-per-block value");
+  if (wgs_per_cu < 0 || wgs_per_cu > 64)
+    return c->fail(DGW_EINVAL, "work-groups per CU out of range (0..64)");
   c->block = elems_per_block;
+  c->wpc = wgs_per_cu;
   c->invalidate_graph();
   return DGW_OK;
 }

@@ -1,7 +1,8 @@
 // Launch-shape autotuner of the stage kernel.
 //
 // Every implemented launch shape (elements per work-group x work-groups per
-// compute unit of the persistent grid) is timed with HIP events on the
+// compute unit of the persistent grid, 0 meaning one work-group per block of
+// elements) is timed with HIP events on the
 // context's stream over real stage launches of the context's own workload,
 // writing into scratch buffers so the solver state is untouched.  The fastest
 // shape is kept; with a cache path the choice is stored in a flat JSON object
@@ -84,23 +85,30 @@ void fill(dgw_ctx *c, StageArgs<real> &a, void *out, void *res) {
 
 }  // namespace
 
-extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *choice) {
+extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path,
+                            int *elems_per_block, int *wgs_per_cu) {
   if (!c) return DGW_EINVAL;
   if (!c->have_mesh || !c->have_mat || !c->have_dt)
     return c->fail(DGW_ESTATE, "mesh, material and dt must be set first");
   char key[128];
   std::snprintf(key, sizeof key, "N%d_fp%d_K%lld_S%d", c->R.N, c->precision,
                 (long long)c->mesh.K, c->nshots);
-  const std::vector<int> opts = stage_block_choices(c->R.N, c->precision);
+  std::vector<std::pair<int, int>> opts;
+  for (int be : stage_block_choices(c->R.N, c->precision))
+    for (int w : {0, 2, 4, 8, 16}) opts.push_back({be, w});
+  auto report = [&](int be, int w) {
+    if (elems_per_block) *elems_per_block = be;
+    if (wgs_per_cu) *wgs_per_cu = w;
+  };
   std::map<std::string, long> cache;
   if (cache_path) {
     cache = read_cache(cache_path);
     auto it = cache.find(key);
     if (it != cache.end())
-      for (int o : opts)
-        if (o == it->second) {
-          int rc = dgw_set_block(c, o);
-          if (choice) *choice = o;
+      for (const auto &o : opts)
+        if (o.first * 1000 + o.second == it->second) {
+          int rc = dgw_set_launch(c, o.first, o.second);
+          report(o.first, o.second);
           return rc;
         }
   }
@@ -114,10 +122,10 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *choice) {
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  int best = opts[0];
+  std::pair<int, int> best = opts[0];
   float best_ms = 1e30f;
   int rc = DGW_OK;
-  for (int o : opts) {
+  for (const auto &o : opts) {
     hipError_t err = hipSuccess;
     const int reps = 10;
     for (int r = 0; r < reps + 2 && err == hipSuccess; ++r) {
@@ -125,11 +133,13 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *choice) {
       if (c->precision == 64) {
         StageArgs<double> a;
         fill(c, a, out, res);
-        err = launch_stage(c->R.N, 64, o, c->nshots, &a, c->stream);
+        err = launch_stage(c->R.N, 64, o.first, o.second, c->ncu, c->nshots, &a,
+                           c->stream);
       } else {
         StageArgs<float> a;
         fill(c, a, out, res);
-        err = launch_stage(c->R.N, 32, o, c->nshots, &a, c->stream);
+        err = launch_stage(c->R.N, 32, o.first, o.second, c->ncu, c->nshots, &a,
+                           c->stream);
       }
     }
     if (err != hipSuccess) {
@@ -152,10 +162,10 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *choice) {
   c->dfree(out);
   c->dfree(res);
   if (rc) return rc;
-  if ((rc = dgw_set_block(c, best))) return rc;
-  if (choice) *choice = best;
+  if ((rc = dgw_set_launch(c, best.first, best.second))) return rc;
+  report(best.first, best.second);
   if (cache_path) {
-    cache[key] = best;
+    cache[key] = best.first * 1000 + best.second;
     if (!write_cache(cache_path, cache))
       return c->fail(DGW_EINVAL, std::string("cannot write ") + cache_path);
   }

@@ -60,7 +60,9 @@ struct dgw_ctx {
   double *d_partial = nullptr;
   int *d_flag = nullptr;
 
-  int block = 0;
+  int block = 0;                    // elements per work-group
+  int wpc = 0;                      // persistent work-groups per CU (0: off)
+  int ncu = 256;
   hipGraphExec_t graph_exec = nullptr;
   bool graph_ok = false;
   int graph_from = 0;

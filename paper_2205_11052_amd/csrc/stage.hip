@@ -1,0 +1,321 @@
+// Fused right-hand side + LSERK stage kernel for gfx950.
+//
+// Work item: a block of BE consecutive elements of one shot.  The items of
+// all shots form one flat list.  The hardware dispatches work-groups to the 8
+// XCDs round-robin, so the linear work-group id is remapped to give every XCD
+// one contiguous range of items: face neighbours (same element, same cube,
+// adjacent cubes) are then mostly processed on the same XCD and their traces
+// are L2 hits.  Two launch forms share the item code: one work-group per item,
+// or a persistent grid of a multiple of 8 work-groups that loop over the
+// items (each work-group stays on one XCD).  They are separate instantiations
+// so the one-item form carries no loop.
+//
+// Per item (256 threads):
+//   1. the block's fields q[BE][9][Np] (contiguous in HBM, read once,
+//      coalesced) and its per-element data go to LDS;
+//   2. one thread per (element, face node): own trace from LDS, neighbour
+//      trace from LDS when the neighbour is in the block, else gathered from
+//      L2/HBM through the face-orientation table; exact Riemann flux in jump
+//      form; the nine lifted flux components (times Fscale) go to LDS;
+//   3. one thread per (element, node): reference derivatives of the nine
+//      fields with Dr, Ds, Dt, the physical volume terms, + LIFT . flux, +
+//      point source, then res = a res + dt rhs and q_out = q_in + b res.
+// q_in and q_out are distinct buffers (neighbour traces are read from q_in
+// while other blocks write q_out); res is element-local and updated in place.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "dgw_internal.h"
+
+namespace dgw {
+
+namespace {
+
+template <int N>
+struct Sz {
+  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Nfp = (N + 1) * (N + 2) / 2;
+};
+
+constexpr int kThreads = 256;
+
+__device__ inline double ricker_d(double tau, double f0, double t0, double amp) {
+  const double pi = 3.14159265358979323846;
+  double a = pi * f0 * (tau - t0);
+  a = a * a;
+  return amp * (1.0 - 2.0 * a) * exp(-a);
+}
+
+// Linear work-group id -> item index such that each XCD (id % 8) owns one
+// contiguous range of items.
+__device__ inline int64_t xcd_item(int64_t L, int64_t total) {
+  const int x = (int)(L & 7);
+  int64_t start = 0;
+  for (int y = 0; y < x; ++y) start += (total - y + 7) >> 3;
+  return start + (L >> 3);
+}
+
+template <int N, typename real, int BE>
+__device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t item,
+                                           int64_t nblk) {
+  constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Nfp;
+  // declared here (not passed in) so every access stays an LDS access
+  __shared__ real sq[BE * 9 * Np];
+  __shared__ real sfl[BE * 9 * NF];
+  __shared__ double smeta[BE * DGW_META];
+  __shared__ int scn[BE * 4];
+  const int shot = (int)(item / nblk);
+  const int64_t step = A.shot_step[shot];
+  if (step >= A.shot_len[shot]) return;            // uniform per work-group
+  const int64_t k0 = (item - (int64_t)shot * nblk) * BE;
+  // never taken (items cover the mesh exactly), but it bounds nE to
+  // [1, BE] for the compiler, which keeps the register count low
+  if (k0 >= A.K) return;
+  const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
+  const real *__restrict__ qin = A.q_in + shot * A.shot_stride;
+  real *__restrict__ qout = A.q_out + shot * A.shot_stride;
+  real *__restrict__ res = A.res + shot * A.shot_stride;
+  const int tid = threadIdx.x;
+
+  for (int t = tid; t < nE * 9 * Np; t += kThreads) sq[t] = qin[k0 * 9 * Np + t];
+  for (int t = tid; t < nE * DGW_META; t += kThreads)
+    smeta[t] = A.meta[k0 * DGW_META + t];
+  for (int t = tid; t < nE * 4; t += kThreads) scn[t] = A.conn[k0 * 4 + t];
+  __syncthreads();
+
+  // ---- faces ----------------------------------------------------------
+  for (int t = tid; t < nE * NF; t += kThreads) {
+    const int e = t / NF, fm = t - e * NF, f = fm / Nfp, m = fm - f * Nfp;
+    const double *g = smeta + e * DGW_META;
+    const real *qe = sq + e * 9 * Np;
+    const int n1 = A.fmask[fm];
+    real qm[9], qp[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) qm[c] = qe[c * Np + n1];
+    const int cn = scn[e * 4 + f];
+    if (cn >= 0) {
+      const int64_t nb = cn >> 5;
+      const int f2 = (cn >> 3) & 3, o = cn & 7;
+      const int n2 = A.nbtab[((f * 4 + f2) * 6 + o) * Nfp + m];
+      const int64_t le = nb - k0;
+      if (le >= 0 && le < nE) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) qp[c] = sq[le * 9 * Np + c * Np + n2];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) qp[c] = qin[(nb * 9 + c) * Np + n2];
+      }
+    } else if (cn == CONN_FREE) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) qp[c] = qm[c];
+#pragma unroll
+      for (int c = 3; c < 9; ++c) qp[c] = -qm[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) qp[c] = (real)0;
+    }
+    const real nx = (real)g[M_NORMAL + 3 * f], ny = (real)g[M_NORMAL + 3 * f + 1],
+               nz = (real)g[M_NORMAL + 3 * f + 2];
+    // jumps [v] = v+ - v-, [t] = (sigma+ - sigma-) n
+    const real dvx = qp[0] - qm[0], dvy = qp[1] - qm[1], dvz = qp[2] - qm[2];
+    const real dsxx = qp[3] - qm[3], dsyy = qp[4] - qm[4], dszz = qp[5] - qm[5];
+    const real dsyz = qp[6] - qm[6], dsxz = qp[7] - qm[7], dsxy = qp[8] - qm[8];
+    const real dtx = dsxx * nx + dsxy * ny + dsxz * nz;
+    const real dty = dsxy * nx + dsyy * ny + dsyz * nz;
+    const real dtz = dsxz * nx + dsyz * ny + dszz * nz;
+    const real dvn = dvx * nx + dvy * ny + dvz * nz;
+    const real dtn = dtx * nx + dty * ny + dtz * nz;
+    const real zp = (real)g[M_ZP], zs = (real)g[M_ZS];
+    const real zpn = (real)g[M_ZPNB + f], zsn = (real)g[M_ZSNB + f];
+    const real izp = (real)g[M_IZPS + f], izs = (real)g[M_IZSS + f];
+    // normal and tangential Riemann amplitudes
+    const real kn = (dtn + zpn * dvn) * izp;
+    const real kTx = (dtx - dtn * nx + zsn * (dvx - dvn * nx)) * izs;
+    const real kTy = (dty - dtn * ny + zsn * (dvy - dvn * ny)) * izs;
+    const real kTz = (dtz - dtn * nz + zsn * (dvz - dvn * nz)) * izs;
+    // dv = v* - v- and dt = t* - t-
+    const real Dvx = kn * nx + kTx, Dvy = kn * ny + kTy, Dvz = kn * nz + kTz;
+    const real ri = (real)g[M_RHOINV], la = (real)g[M_LAM], mu = (real)g[M_MU];
+    const real fs = (real)g[M_FSCALE + f];
+    real fl[9];
+    fl[0] = (zp * kn * nx + zs * kTx) * ri;
+    fl[1] = (zp * kn * ny + zs * kTy) * ri;
+    fl[2] = (zp * kn * nz + zs * kTz) * ri;
+    const real ndv = nx * Dvx + ny * Dvy + nz * Dvz;
+    fl[3] = la * ndv + 2 * mu * Dvx * nx;
+    fl[4] = la * ndv + 2 * mu * Dvy * ny;
+    fl[5] = la * ndv + 2 * mu * Dvz * nz;
+    fl[6] = mu * (Dvy * nz + Dvz * ny);
+    fl[7] = mu * (Dvx * nz + Dvz * nx);
+    fl[8] = mu * (Dvx * ny + Dvy * nx);
+    real *dst = sfl + e * 9 * NF + fm;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dst[c * NF] = fs * fl[c];
+  }
+  __syncthreads();
+
+  // ---- volume + lift + RK update --------------------------------------
+  for (int t = tid; t < nE * Np; t += kThreads) {
+    const int e = t / Np, i = t - e * Np;
+    const real *qe = sq + e * 9 * Np;
+    const double *g = smeta + e * DGW_META;
+    real dr[9], ds[9], dt[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dr[c] = ds[c] = dt[c] = (real)0;
+    for (int j = 0; j < Np; ++j) {
+      const real a0 = A.DrT[j * Np + i], a1 = A.DsT[j * Np + i],
+                 a2 = A.DtT[j * Np + i];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        const real v = qe[c * Np + j];
+        dr[c] += a0 * v;
+        ds[c] += a1 * v;
+        dt[c] += a2 * v;
+      }
+    }
+    real X[9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) X[u] = (real)g[M_XINV + u];
+    // d/dx_b of field c
+    auto D = [&](int c, int b) -> real {
+      return X[b] * dr[c] + X[3 + b] * ds[c] + X[6 + b] * dt[c];
+    };
+    const real ri = (real)g[M_RHOINV], la = (real)g[M_LAM], mu = (real)g[M_MU];
+    const real divv = D(0, 0) + D(1, 1) + D(2, 2);
+    real rhs[9];
+    rhs[0] = (D(3, 0) + D(8, 1) + D(7, 2)) * ri;
+    rhs[1] = (D(8, 0) + D(4, 1) + D(6, 2)) * ri;
+    rhs[2] = (D(7, 0) + D(6, 1) + D(5, 2)) * ri;
+    rhs[3] = la * divv + 2 * mu * D(0, 0);
+    rhs[4] = la * divv + 2 * mu * D(1, 1);
+    rhs[5] = la * divv + 2 * mu * D(2, 2);
+    rhs[6] = mu * (D(1, 2) + D(2, 1));
+    rhs[7] = mu * (D(0, 2) + D(2, 0));
+    rhs[8] = mu * (D(0, 1) + D(1, 0));
+    const real *fle = sfl + e * 9 * NF;
+    for (int fm = 0; fm < NF; ++fm) {
+      const real l = A.LIFTT[fm * Np + i];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) rhs[c] += l * fle[c * NF + fm];
+    }
+    const int64_t k = k0 + e;
+    if (A.src_elem[shot] == k) {
+      const double *sp = A.src_par + 10 * shot;
+      const double s = ricker_d(((double)step + A.rk_c) * A.dt, sp[6], sp[7], sp[8]);
+      const double w = s * A.src_vec[shot * Np + i];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) rhs[3 + c] += (real)(w * sp[c]);
+    }
+    const real ra = (real)A.rk_a, rb = (real)A.rk_b, rdt = (real)A.dt;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const int64_t idx = (k * 9 + c) * Np + i;
+      // stage 1 (a = 0) never reads res, so stale values cannot leak in
+      const real r = (A.rk_a == 0.0) ? rdt * rhs[c] : ra * res[idx] + rdt * rhs[c];
+      res[idx] = r;
+      qout[idx] = qe[c * Np + i] + rb * r;
+    }
+  }
+}
+
+// One work-group per item.
+template <int N, typename real, int BE>
+__global__ void __launch_bounds__(kThreads)
+stage_kernel(StageArgs<real> A, int64_t nblk, int64_t total) {
+  stage_item<N, real, BE>(A, xcd_item(blockIdx.x, total), nblk);
+}
+
+// Persistent grid (a multiple of 8 work-groups) looping over the items.
+template <int N, typename real, int BE>
+__global__ void __launch_bounds__(kThreads)
+stage_kernel_persistent(StageArgs<real> A, int64_t nblk, int64_t total) {
+  for (int64_t L = blockIdx.x; L < total; L += gridDim.x) {
+    stage_item<N, real, BE>(A, xcd_item(L, total), nblk);
+    __syncthreads();   // LDS is reused by the next item
+  }
+}
+
+// elements per work-group: the largest BE with BE * Np <= 256 and the LDS
+// tile (fields, lifted fluxes, per-element data) within 64 KB, and half of it
+template <int N, typename real>
+struct Shapes {
+  static constexpr int Np = Sz<N>::Np, NF = 4 * Sz<N>::Nfp;
+  static constexpr int per = (9 * Np + 9 * NF) * (int)sizeof(real) + DGW_META * 8 + 16;
+  static constexpr int cap1 = kThreads / Np, cap2 = 65536 / per;
+  static constexpr int a = cap1 < cap2 ? cap1 : cap2;
+  static constexpr int b = a / 2 > 0 ? a / 2 : 1;
+};
+
+template <int N, typename real>
+hipError_t launch_t(int be, int wpc, int ncu, int nshots, const StageArgs<real> &a,
+                    hipStream_t st) {
+  constexpr int A_ = Shapes<N, real>::a, B_ = Shapes<N, real>::b;
+  if (be != A_ && be != B_) return hipErrorInvalidValue;
+  const int64_t nblk = (a.K + be - 1) / be;
+  const int64_t total = nblk * nshots;
+  const int64_t pers = ((int64_t)ncu * wpc + 7) / 8 * 8;
+  if (wpc > 0 && pers < total) {
+    if (be == A_)
+      hipLaunchKernelGGL((stage_kernel_persistent<N, real, A_>), dim3((unsigned)pers),
+                         dim3(kThreads), 0, st, a, nblk, total);
+    else
+      hipLaunchKernelGGL((stage_kernel_persistent<N, real, B_>), dim3((unsigned)pers),
+                         dim3(kThreads), 0, st, a, nblk, total);
+  } else {
+    if (be == A_)
+      hipLaunchKernelGGL((stage_kernel<N, real, A_>), dim3((unsigned)total),
+                         dim3(kThreads), 0, st, a, nblk, total);
+    else
+      hipLaunchKernelGGL((stage_kernel<N, real, B_>), dim3((unsigned)total),
+                         dim3(kThreads), 0, st, a, nblk, total);
+  }
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_r(int N, int be, int wpc, int ncu, int nshots, const void *args,
+                    hipStream_t st) {
+  const StageArgs<real> &a = *(const StageArgs<real> *)args;
+  switch (N) {
+    case 1: return launch_t<1, real>(be, wpc, ncu, nshots, a, st);
+    case 2: return launch_t<2, real>(be, wpc, ncu, nshots, a, st);
+    case 3: return launch_t<3, real>(be, wpc, ncu, nshots, a, st);
+    case 4: return launch_t<4, real>(be, wpc, ncu, nshots, a, st);
+    case 5: return launch_t<5, real>(be, wpc, ncu, nshots, a, st);
+    case 6: return launch_t<6, real>(be, wpc, ncu, nshots, a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename real>
+std::vector<int> choices_r(int N) {
+  switch (N) {
+    case 1: return {Shapes<1, real>::a, Shapes<1, real>::b};
+    case 2: return {Shapes<2, real>::a, Shapes<2, real>::b};
+    case 3: return {Shapes<3, real>::a, Shapes<3, real>::b};
+    case 4: return {Shapes<4, real>::a, Shapes<4, real>::b};
+    case 5: return {Shapes<5, real>::a, Shapes<5, real>::b};
+    case 6: return {Shapes<6, real>::a, Shapes<6, real>::b};
+  }
+  return {};
+}
+
+}  // namespace
+
+hipError_t launch_stage(int N, int precision, int be, int wpc, int ncu, int nshots,
+                        const void *args, hipStream_t st) {
+  if (precision == 64) return launch_r<double>(N, be, wpc, ncu, nshots, args, st);
+  return launch_r<float>(N, be, wpc, ncu, nshots, args, st);
+}
+
+std::vector<int> stage_block_choices(int N, int precision) {
+  return precision == 64 ? choices_r<double>(N) : choices_r<float>(N);
+}
+
+int default_block(int N, int precision) {
+  std::vector<int> c = stage_block_choices(N, precision);
+  return c.empty() ? 0 : c[0];
+}
+
+}  // namespace dgw

@@ -243,15 +243,17 @@ class Solver:
 
     # -- launch shape and timing ---------------------------------------------
     def autotune(self, cache_path=None):
-        ch = C.c_int()
+        """Time the launch shapes; returns (elements per work-group,
+        persistent work-groups per CU)."""
+        be, w = C.c_int(), C.c_int()
         self._check(self.lib.dgw_autotune(
             self._ctx, cache_path.encode() if cache_path else None,
-            C.byref(ch)), "dgw_autotune")
-        return ch.value
+            C.byref(be), C.byref(w)), "dgw_autotune")
+        return be.value, w.value
 
-    def set_block(self, elems):
-        self._check(self.lib.dgw_set_block(self._ctx, int(elems)),
-                    "dgw_set_block")
+    def set_launch(self, elems=0, wgs_per_cu=0):
+        self._check(self.lib.dgw_set_launch(self._ctx, int(elems),
+                                            int(wgs_per_cu)), "dgw_set_launch")
 
     def enable_timing(self, on=True):
         self._check(self.lib.dgw_enable_timing(self._ctx, 1 if on else 0),
