@@ -23,6 +23,7 @@ CPU baseline: the CPU oracle (plain PyTorch FP64) timed on the host on a
 bounded sample of the same workload (two LSERK4 steps of the full mesh).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                       [--no-forms] [--shape K,E,W] [--copy-probe]
 """
 
 import argparse
@@ -46,7 +47,7 @@ def stage_bytes(K, Np, real_bytes, nshots=1):
     return nshots * K * 4 * 9 * Np * real_bytes + K * META_BYTES
 
 
-def build_solver(w, precision, nshots=1, stream=None, shots=None):
+def build_solver(w, precision, nshots=1, stream=None, shots=None, shape=None):
     from paper_2205_11052_amd import Solver
     s = Solver(w["N"], precision, nshots, stream=stream)
     s.set_mesh_dict(w["mesh"])
@@ -58,10 +59,26 @@ def build_solver(w, precision, nshots=1, stream=None, shots=None):
         n = 0 if shots is None else int(shots[1][i])
         s.set_source(i, pos, w["f0"], w["t0"], w["amp"], nsteps=n)
         s.set_receivers(i, w["receivers"], 4096)
-    # launch shape (elements per work-group, persistent grid) chosen by the
-    # library's autotuner on this very workload
-    s.shape = s.autotune()
+    # launch shape (elements per work-group, persistent grid): given, or
+    # chosen by the library's autotuner on this very workload
+    if shape is None:
+        s.shape = s.autotune()
+    else:
+        s.set_launch(*shape)
+        s.shape = tuple(shape)
     return s
+
+
+def copy_probe(torch, nbytes=1 << 30, reps=3):
+    """A plain device-to-device copy of known size (reads and writes nbytes
+    per launch); profiling it calibrates the HBM byte counters."""
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_per_launch": nbytes, "launches": reps}),
+          flush=True)
 
 
 def timed_steps(torch, s, stream, steps, warmup):
@@ -114,7 +131,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--shape", default=None,  # kernel,elements,wgs_per_cu
+                    help="launch shape 'kernel,elements,wgs_per_cu' (skips the autotuner)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU "
@@ -126,6 +146,10 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(torch)
+        return
+    shape = tuple(int(x) for x in args.shape.split(",")) if args.shape else None
     stream = torch.cuda.Stream()
     w = W.build_workload("c1_layered_n24")
     K, N = w["K"], w["N"]
@@ -133,10 +157,7 @@ def main():
     dof = 9 * Np * K
 
     with torch.cuda.stream(stream):
-        s = build_solver(w, 64, stream=stream.cuda_stream)
-        if args.block:
-            s.set_launch(args.block, 0)
-            s.shape = (args.block, 0)
+        s = build_solver(w, 64, stream=stream.cuda_stream, shape=shape)
         sec, wall = timed_steps(torch, s, stream, args.steps, args.warmup)
         kms, nl = kernel_avg_ms(s)
         s.check_finite()
@@ -161,14 +182,15 @@ def main():
                      "kernel_avg_ms": round(kms, 5),
                      "launches_timed": nl,
                      "bytes_per_launch": bytes_launch,
-                     "launch_shape": {"elements_per_workgroup": shape64[0],
-                                      "persistent_wgs_per_cu": shape64[1]}},
+                     "launch_shape": {"kernel": shape64[0],
+                                      "elements_per_workgroup": shape64[1],
+                                      "persistent_wgs_per_cu": shape64[2]}},
     }
     del s
     if not args.no_forms:
         forms = {}
         with torch.cuda.stream(stream):
-            s32 = build_solver(w, 32, stream=stream.cuda_stream)
+            s32 = build_solver(w, 32, stream=stream.cuda_stream, shape=shape)
             sec32, _ = timed_steps(torch, s32, stream, args.steps, args.warmup)
             k32, _ = kernel_avg_ms(s32)
             shape32 = s32.shape
@@ -186,7 +208,7 @@ def main():
         bsteps = max(10, args.steps // 10)
         with torch.cuda.stream(stream):
             sb = build_solver(w, 32, nshots=nb, stream=stream.cuda_stream,
-                              shots=(pos, lens))
+                              shots=(pos, lens), shape=shape)
             secb, _ = timed_steps(torch, sb, stream, bsteps, 2)
             kb, _ = kernel_avg_ms(sb, 2)
             shapeb = sb.shape

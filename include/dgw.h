@@ -180,16 +180,19 @@ int dgw_adjoint(dgw_ctx *ctx, double *g_rho, double *g_lam, double *g_mu);
  * from / written to that JSON file (keyed by order, precision, element count
  * and shot count).  The chosen shape is returned through the two pointers
  * (either may be NULL); see dgw_set_launch. */
-int dgw_autotune(dgw_ctx *ctx, const char *cache_path, int *elems_per_block,
-                 int *wgs_per_cu);
+int dgw_autotune(dgw_ctx *ctx, const char *cache_path, int *kernel,
+                 int *elems_per_block, int *wgs_per_cu);
 
-/* Launch shape of the stage kernel: elements per work-group (0 = default;
- * DGW_EINVAL for values the kernel does not implement) and work-groups per
+/* Launch shape of the stage kernel.  kernel 0: one thread per (element,
+ * node) with the block's fields and lifted fluxes staged in LDS; then
+ * elems_per_block is the elements per work-group (0 = default; DGW_EINVAL for
+ * values the kernel does not implement) and wgs_per_cu the work-groups per
  * compute unit of a persistent grid (0 = one work-group per block of
  * elements, the default; 1..64 = a persistent grid of that many work-groups
  * per CU, rounded up to a multiple of 8, looping over the blocks of all
- * shots). */
-int dgw_set_launch(dgw_ctx *ctx, int elems_per_block, int wgs_per_cu);
+ * shots).  Kernel variants other than 0 that this build does not provide
+ * for the context's order and precision give DGW_EINVAL. */
+int dgw_set_launch(dgw_ctx *ctx, int kernel, int elems_per_block, int wgs_per_cu);
 
 /* Average duration in milliseconds of the stage-kernel launches made by the
  * last dgw_step call, measured with HIP events on the context's stream

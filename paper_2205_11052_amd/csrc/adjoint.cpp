@@ -146,11 +146,11 @@ int stage_explicit(dgw_ctx *c, const void *in, void *out, void *res, int stage) 
   if (c->precision == 64) {
     StageArgs<double> a;
     fill_stage(c, a, in, out, res, stage);
-    e = launch_stage(c->R.N, 64, c->block, c->wpc, c->ncu, c->nshots, &a, c->stream);
+    e = launch_stage(c->kernel, c->R.N, 64, c->block, c->wpc, c->ncu, c->nshots, &a, c->stream);
   } else {
     StageArgs<float> a;
     fill_stage(c, a, in, out, res, stage);
-    e = launch_stage(c->R.N, 32, c->block, c->wpc, c->ncu, c->nshots, &a, c->stream);
+    e = launch_stage(c->kernel, c->R.N, 32, c->block, c->wpc, c->ncu, c->nshots, &a, c->stream);
   }
   if (e != hipSuccess) return c->hipfail(e, "stage kernel launch (recompute)");
   return DGW_OK;

@@ -339,11 +339,11 @@ int dgw_ctx::enqueue_step(int from, bool timed) {
     if (precision == 64) {
       StageArgs<double> a;
       fill_stage_args(this, a, i, from);
-      e = launch_stage(R.N, 64, block, wpc, ncu, nshots, &a, stream);
+      e = launch_stage(kernel, R.N, 64, block, wpc, ncu, nshots, &a, stream);
     } else {
       StageArgs<float> a;
       fill_stage_args(this, a, i, from);
-      e = launch_stage(R.N, 32, block, wpc, ncu, nshots, &a, stream);
+      e = launch_stage(kernel, R.N, 32, block, wpc, ncu, nshots, &a, stream);
     }
     if (e != hipSuccess) return hipfail(e, "stage kernel launch");
     if (timed && ev_pool_used + 2 <= (int)ev_pool.size()) {
@@ -799,8 +799,11 @@ int dgw_ref_operators(int order, double *Dr, double *Ds, double *Dt, double *M,
   return DGW_OK;
 }
 
-int dgw_set_launch(dgw_ctx *c, int elems_per_block, int wgs_per_cu) {
+int dgw_set_launch(dgw_ctx *c, int kernel, int elems_per_block, int wgs_per_cu) {
   if (!c) return DGW_EINVAL;
+  if (!stage_kernel_supported(kernel, c->R.N, c->precision))
+    return c->fail(DGW_EINVAL, "stage kernel not available for this order/precision");
+  c->kernel = kernel;
   std::vector<int> ch = stage_block_choices(c->R.N, c->precision);
   if (elems_per_block == 0) elems_per_block = ch[0];
   if (std::find(ch.begin(), ch.end(), elems_per_block) == ch.end())

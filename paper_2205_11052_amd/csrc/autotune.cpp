@@ -1,8 +1,9 @@
 // Launch-shape autotuner of the stage kernel.
 //
-// Every implemented launch shape (elements per work-group x work-groups per
-// compute unit of the persistent grid, 0 meaning one work-group per block of
-// elements) is timed with HIP events on the
+// Every implemented launch shape -- the node-per-thread kernel with each
+// elements-per-work-group value x work-groups per compute unit of the
+// persistent grid (0 meaning one work-group per block of elements), and the
+// lane-per-field kernel where it supports the order -- is timed with HIP events on the
 // context's stream over real stage launches of the context's own workload,
 // writing into scratch buffers so the solver state is untouched.  The fastest
 // shape is kept; with a cache path the choice is stored in a flat JSON object
@@ -85,7 +86,12 @@ void fill(dgw_ctx *c, StageArgs<real> &a, void *out, void *res) {
 
 }  // namespace
 
-extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path,
+struct Shape {
+  int kernel, be, wpc;
+  long code() const { return kernel * 1000000L + be * 1000L + wpc; }
+};
+
+extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *kernel,
                             int *elems_per_block, int *wgs_per_cu) {
   if (!c) return DGW_EINVAL;
   if (!c->have_mesh || !c->have_mat || !c->have_dt)
@@ -93,12 +99,13 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path,
   char key[128];
   std::snprintf(key, sizeof key, "N%d_fp%d_K%lld_S%d", c->R.N, c->precision,
                 (long long)c->mesh.K, c->nshots);
-  std::vector<std::pair<int, int>> opts;
+  std::vector<Shape> opts;
   for (int be : stage_block_choices(c->R.N, c->precision))
-    for (int w : {0, 2, 4, 8, 16}) opts.push_back({be, w});
-  auto report = [&](int be, int w) {
-    if (elems_per_block) *elems_per_block = be;
-    if (wgs_per_cu) *wgs_per_cu = w;
+    for (int w : {0, 2, 4, 8, 16}) opts.push_back({0, be, w});
+  auto report = [&](const Shape &o) {
+    if (kernel) *kernel = o.kernel;
+    if (elems_per_block) *elems_per_block = o.be;
+    if (wgs_per_cu) *wgs_per_cu = o.wpc;
   };
   std::map<std::string, long> cache;
   if (cache_path) {
@@ -106,9 +113,9 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path,
     auto it = cache.find(key);
     if (it != cache.end())
       for (const auto &o : opts)
-        if (o.first * 1000 + o.second == it->second) {
-          int rc = dgw_set_launch(c, o.first, o.second);
-          report(o.first, o.second);
+        if (o.code() == it->second) {
+          int rc = dgw_set_launch(c, o.kernel, o.be, o.wpc);
+          report(o);
           return rc;
         }
   }
@@ -122,7 +129,7 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path,
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  std::pair<int, int> best = opts[0];
+  Shape best = opts[0];
   float best_ms = 1e30f;
   int rc = DGW_OK;
   for (const auto &o : opts) {
@@ -133,12 +140,12 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path,
       if (c->precision == 64) {
         StageArgs<double> a;
         fill(c, a, out, res);
-        err = launch_stage(c->R.N, 64, o.first, o.second, c->ncu, c->nshots, &a,
+        err = launch_stage(o.kernel, c->R.N, 64, o.be, o.wpc, c->ncu, c->nshots, &a,
                            c->stream);
       } else {
         StageArgs<float> a;
         fill(c, a, out, res);
-        err = launch_stage(c->R.N, 32, o.first, o.second, c->ncu, c->nshots, &a,
+        err = launch_stage(o.kernel, c->R.N, 32, o.be, o.wpc, c->ncu, c->nshots, &a,
                            c->stream);
       }
     }
@@ -162,10 +169,10 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path,
   c->dfree(out);
   c->dfree(res);
   if (rc) return rc;
-  if ((rc = dgw_set_launch(c, best.first, best.second))) return rc;
-  report(best.first, best.second);
+  if ((rc = dgw_set_launch(c, best.kernel, best.be, best.wpc))) return rc;
+  report(best);
   if (cache_path) {
-    cache[key] = best.first * 1000 + best.second;
+    cache[key] = best.code();
     if (!write_cache(cache_path, cache))
       return c->fail(DGW_EINVAL, std::string("cannot write ") + cache_path);
   }

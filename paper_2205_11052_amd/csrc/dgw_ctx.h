@@ -60,6 +60,7 @@ struct dgw_ctx {
   double *d_partial = nullptr;
   int *d_flag = nullptr;
 
+  int kernel = 0;                   // stage kernel variant (0: node per thread)
   int block = 0;                    // elements per work-group
   int wpc = 0;                      // persistent work-groups per CU (0: off)
   int ncu = 256;

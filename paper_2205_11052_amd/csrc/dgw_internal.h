@@ -136,10 +136,12 @@ hipError_t launch_set_steps(int64_t *steps, int nshots, int64_t value,
                             hipStream_t st);
 
 // Launchers (kernels.hip); return the launch error.
-// be = elements per work-group; wpc = persistent work-groups per compute
-// unit (0: one work-group per block of elements); ncu = compute units.
-hipError_t launch_stage(int N, int precision, int be, int wpc, int ncu,
-                        int nshots, const void *args, hipStream_t st);
+// kernel 0 (node per thread, LDS tiles): be = elements per work-group,
+// wpc = persistent work-groups per compute unit (0: one work-group per block
+// of elements).  ncu = compute units.
+hipError_t launch_stage(int kernel, int N, int precision, int be, int wpc,
+                        int ncu, int nshots, const void *args, hipStream_t st);
+bool stage_kernel_supported(int kernel, int N, int precision);
 hipError_t launch_receivers(int precision, int nshots, const RecArgs &a,
                             hipStream_t st);
 hipError_t launch_energy(int precision, const void *q, int64_t K, int Np,

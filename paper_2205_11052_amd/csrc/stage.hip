@@ -303,10 +303,15 @@ std::vector<int> choices_r(int N) {
 
 }  // namespace
 
-hipError_t launch_stage(int N, int precision, int be, int wpc, int ncu, int nshots,
-                        const void *args, hipStream_t st) {
+hipError_t launch_stage(int kernel, int N, int precision, int be, int wpc, int ncu,
+                        int nshots, const void *args, hipStream_t st) {
+  if (!stage_kernel_supported(kernel, N, precision)) return hipErrorInvalidValue;
   if (precision == 64) return launch_r<double>(N, be, wpc, ncu, nshots, args, st);
   return launch_r<float>(N, be, wpc, ncu, nshots, args, st);
+}
+
+bool stage_kernel_supported(int kernel, int N, int precision) {
+  return kernel == 0 && N >= 1 && N <= DGW_MAX_ORDER && (precision == 64 || precision == 32);
 }
 
 std::vector<int> stage_block_choices(int N, int precision) {

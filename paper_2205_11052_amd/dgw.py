@@ -243,16 +243,16 @@ class Solver:
 
     # -- launch shape and timing ---------------------------------------------
     def autotune(self, cache_path=None):
-        """Time the launch shapes; returns (elements per work-group,
-        persistent work-groups per CU)."""
-        be, w = C.c_int(), C.c_int()
+        """Time the launch shapes; returns (kernel, elements per work-group,
+        persistent work-groups per CU) of the fastest."""
+        k, be, w = C.c_int(), C.c_int(), C.c_int()
         self._check(self.lib.dgw_autotune(
             self._ctx, cache_path.encode() if cache_path else None,
-            C.byref(be), C.byref(w)), "dgw_autotune")
-        return be.value, w.value
+            C.byref(k), C.byref(be), C.byref(w)), "dgw_autotune")
+        return k.value, be.value, w.value
 
-    def set_launch(self, elems=0, wgs_per_cu=0):
-        self._check(self.lib.dgw_set_launch(self._ctx, int(elems),
+    def set_launch(self, kernel=0, elems=0, wgs_per_cu=0):
+        self._check(self.lib.dgw_set_launch(self._ctx, int(kernel), int(elems),
                                             int(wgs_per_cu)), "dgw_set_launch")
 
     def enable_timing(self, on=True):

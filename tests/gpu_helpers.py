@@ -22,11 +22,13 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def gpu_solver(mesh, N, rho, lam, mu, dt, precision=64, nshots=1):
+def gpu_solver(mesh, N, rho, lam, mu, dt, precision=64, nshots=1, kernel=0):
     s = Solver(N, precision, nshots)
     s.set_mesh_dict(mesh)
     s.set_material(rho, lam, mu)
     s.set_dt(dt)
+    if kernel:
+        s.set_launch(kernel)
     return s
 
 

@@ -10,6 +10,7 @@ import pytest
 import torch
 
 import workloads as W
+from paper_2205_11052_amd.dgw import DGWError
 from gpu_helpers import (gpu_solver, oracle_problem, oracle_run, rel_l2,
                          random_fields, say)
 
@@ -50,7 +51,7 @@ def test_c0_periodic_plane_wave_fp64():
     s.check_finite()
 
 
-@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("N", range(1, 7))
 def test_all_orders_all_boundaries_fp64(N):
     mesh = W.kuhn_cube(2, 1.0)          # free-surface top, absorbing sides
     K = mesh["etov"].shape[0]
@@ -107,9 +108,10 @@ def test_reduced_layered_source_receivers_fp64():
 
 
 def test_full_size_layered_fp64_bench_launch():
-    """Full 82944-element mesh at order 4 in the benchmark's launch shape:
-    random fields everywhere (every face type and element exercised), the
-    source and receivers active, two steps against the oracle."""
+    """Full 82944-element mesh at order 4 in every launch shape the
+    benchmark's autotuner can pick: random fields everywhere (every face
+    type and element exercised), the source and receivers active, two steps
+    against the oracle."""
     w = W.build_workload("c1_layered_n24")
     say("case full c1 fp64 K=%d" % w["K"])
     P = oracle_problem(w["mesh"], w["N"])
@@ -117,19 +119,20 @@ def test_full_size_layered_fp64_bench_launch():
     P.set_source(w["source"], w["f0"], 0.05, w["amp"])
     P.set_receivers(w["receivers"])
     q0 = random_fields(w["K"], P.Np, 7)
+    q_ora, tr_ora = oracle_run(P, q0, w["rho"], w["lam"], w["mu"], dt, 2,
+                               record=True)
+    shapes = [(0, be, wpc) for be in (7, 3) for wpc in (0, 2, 4, 8, 16)]
     s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
     s.set_source(0, w["source"], w["f0"], 0.05, w["amp"])
     s.set_receivers(0, w["receivers"], 8)
-    s.set_fields(0, q0)
-    s.step(2)
-    q_gpu = s.get_fields(0)
-    tr = s.read_traces(0)
-    q_ora, tr_ora = oracle_run(P, q0, w["rho"], w["lam"], w["mu"], dt, 2,
-                               record=True)
-    err = rel_l2(q_gpu, q_ora)
-    terr = rel_l2(tr, tr_ora)
-    say("full c1 fields %.3e traces %.3e" % (err, terr))
-    assert err <= FP64_TOL and terr <= FP64_TOL
+    for shape in shapes:
+        s.set_launch(*shape)
+        s.set_fields(0, q0)
+        s.step(2)
+        err = rel_l2(s.get_fields(0), q_ora)
+        terr = rel_l2(s.read_traces(0), tr_ora)
+        say("full c1 shape %s fields %.3e traces %.3e" % (shape, err, terr))
+        assert err <= FP64_TOL and terr <= FP64_TOL
 
 
 def test_fp32_error_against_fp64_oracle():
@@ -177,11 +180,11 @@ def test_graph_replay_equals_eager_and_block_shapes_agree():
     dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
     q0 = random_fields(w["K"], P.Np, 5)
     outs = []
-    shapes = ((False, 0, 0), (True, 0, 0), (False, 3, 0), (False, 7, 4),
-              (False, 3, 1))
-    for timing, block, wpc in shapes:
+    shapes = ((False, 0, 0, 0), (True, 0, 0, 0), (False, 0, 3, 0),
+              (False, 0, 7, 4), (False, 0, 3, 1))
+    for timing, kernel, block, wpc in shapes:
         s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
-        s.set_launch(block, wpc)
+        s.set_launch(kernel, block, wpc)
         s.enable_timing(timing)
         s.set_source(0, w["source"], w["f0"], w["t0"], w["amp"])
         s.set_fields(0, q0)
@@ -192,6 +195,10 @@ def test_graph_replay_equals_eager_and_block_shapes_agree():
             assert n == 5 * 23 and ms > 0
     for o in outs[1:]:
         assert np.array_equal(outs[0], o)
+    # a kernel variant this build does not provide is refused
+    with pytest.raises(DGWError) as ei:
+        s.set_launch(1, 0, 0)
+    assert ei.value.status == "DGW_EINVAL"
 
 
 @pytest.mark.parametrize("precision", [64, 32])
@@ -207,7 +214,8 @@ def test_batched_shots_match_single_shot_runs(precision):
     rec = np.array([[0.4, 0.4, 1.0], [0.6, 0.2, 1.0]])
     say("case batched shots precision=%d" % precision)
     b = gpu_solver(mesh, N, rho, lam, mu, dt, precision, nshots=3)
-    b.set_launch(0, 2)      # persistent grid looping over (shot, block) items
+    # persistent grid looping over (shot, block) items
+    b.set_launch(0, 0, 2)
     for i in range(3):
         b.set_source(i, srcs[i], 6.0, 0.1, 1.0, nsteps=lens[i])
         b.set_receivers(i, rec, 20)
