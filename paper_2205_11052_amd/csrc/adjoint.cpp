@@ -114,42 +114,16 @@ void fill_adj(dgw_ctx *c, AdjArgs<real> &a, const void *q, void *lq, void *lr,
   a.dt = c->dt;
 }
 
-template <typename real>
-void fill_stage(dgw_ctx *c, StageArgs<real> &a, const void *in, void *out,
-                void *res, int stage) {
-  a.q_in = (const real *)in;
-  a.q_out = (real *)out;
-  a.res = (real *)res;
-  a.meta = c->d_meta;
-  a.conn = c->d_conn;
-  a.nbtab = c->d_nbtab;
-  a.DrT = (const real *)c->d_DrT;
-  a.DsT = (const real *)c->d_DsT;
-  a.DtT = (const real *)c->d_DtT;
-  a.LIFTT = (const real *)c->d_LIFTT;
-  a.fmask = c->d_fmask;
-  a.K = c->mesh.K;
-  a.shot_stride = c->mesh.K * 9 * c->R.Np;
-  a.shot_step = c->adj->d_aux;
-  a.shot_len = c->d_len;
-  a.src_elem = c->d_src_elem;
-  a.src_vec = c->d_src_vec;
-  a.src_par = c->d_src_par;
-  a.rk_a = rk_a()[stage];
-  a.rk_b = rk_b()[stage];
-  a.rk_c = rk_c()[stage];
-  a.dt = c->dt;
-}
 
 int stage_explicit(dgw_ctx *c, const void *in, void *out, void *res, int stage) {
   hipError_t e;
   if (c->precision == 64) {
     StageArgs<double> a;
-    fill_stage(c, a, in, out, res, stage);
+    stage_args(c, a, in, out, res, c->adj->d_aux, stage);
     e = launch_stage(c->kernel, c->R.N, 64, c->block, c->wpc, c->ncu, c->nshots, &a, c->stream);
   } else {
     StageArgs<float> a;
-    fill_stage(c, a, in, out, res, stage);
+    stage_args(c, a, in, out, res, c->adj->d_aux, stage);
     e = launch_stage(c->kernel, c->R.N, 32, c->block, c->wpc, c->ncu, c->nshots, &a, c->stream);
   }
   if (e != hipSuccess) return c->hipfail(e, "stage kernel launch (recompute)");

@@ -301,32 +301,6 @@ int dgw_ctx::material_meta() {
   return upload(d_meta, g.data(), sizeof(double) * g.size());
 }
 
-template <typename real>
-static void fill_stage_args(dgw_ctx *c, StageArgs<real> &a, int stage,
-                            int from) {
-  a.q_in = (const real *)c->d_q[from];
-  a.q_out = (real *)c->d_q[1 - from];
-  a.res = (real *)c->d_res;
-  a.meta = c->d_meta;
-  a.conn = c->d_conn;
-  a.nbtab = c->d_nbtab;
-  a.DrT = (const real *)c->d_DrT;
-  a.DsT = (const real *)c->d_DsT;
-  a.DtT = (const real *)c->d_DtT;
-  a.LIFTT = (const real *)c->d_LIFTT;
-  a.fmask = c->d_fmask;
-  a.K = c->mesh.K;
-  a.shot_stride = c->mesh.K * 9 * c->R.Np;
-  a.shot_step = c->d_step;
-  a.shot_len = c->d_len;
-  a.src_elem = c->d_src_elem;
-  a.src_vec = c->d_src_vec;
-  a.src_par = c->d_src_par;
-  a.rk_a = kRkA[stage];
-  a.rk_b = kRkB[stage];
-  a.rk_c = kRkC[stage];
-  a.dt = c->dt;
-}
 
 // Enqueue one step (5 stages + receivers) starting from buffer `from`;
 // returns the buffer holding the result.
@@ -338,11 +312,11 @@ int dgw_ctx::enqueue_step(int from, bool timed) {
     }
     if (precision == 64) {
       StageArgs<double> a;
-      fill_stage_args(this, a, i, from);
+      stage_args(this, a, d_q[from], d_q[1 - from], d_res, d_step, i);
       e = launch_stage(kernel, R.N, 64, block, wpc, ncu, nshots, &a, stream);
     } else {
       StageArgs<float> a;
-      fill_stage_args(this, a, i, from);
+      stage_args(this, a, d_q[from], d_q[1 - from], d_res, d_step, i);
       e = launch_stage(kernel, R.N, 32, block, wpc, ncu, nshots, &a, stream);
     }
     if (e != hipSuccess) return hipfail(e, "stage kernel launch");
@@ -427,7 +401,7 @@ int dgw_create(int order, int precision, int nshots, void *hip_stream,
     delete c;
     return DGW_EINVAL;
   }
-  c->block = default_block(order, precision);
+  c->block = default_block(0, order, precision);
   *out = c;
   return DGW_OK;
 }
@@ -480,11 +454,13 @@ int dgw_set_mesh(dgw_ctx *c, int64_t nvert, const double *vxyz, int64_t K,
   c->d_meta = (double *)c->dalloc(sizeof(double) * c->mesh.geo.size());
   c->d_conn = (int32_t *)c->dalloc(sizeof(int32_t) * c->mesh.conn.size());
   c->d_nbtab = (int32_t *)c->dalloc(sizeof(int32_t) * c->mesh.nbtab.size());
-  if (!c->d_meta || !c->d_conn || !c->d_nbtab)
+  c->d_nbnode = (uint8_t *)c->dalloc(c->mesh.nbnode.size());
+  if (!c->d_meta || !c->d_conn || !c->d_nbtab || !c->d_nbnode)
     return c->fail(DGW_ENOMEM, "device allocation failed (mesh)");
   if ((rc = c->upload(c->d_meta, c->mesh.geo.data(), sizeof(double) * c->mesh.geo.size()))) return rc;
   if ((rc = c->upload(c->d_conn, c->mesh.conn.data(), sizeof(int32_t) * c->mesh.conn.size()))) return rc;
   if ((rc = c->upload(c->d_nbtab, c->mesh.nbtab.data(), sizeof(int32_t) * c->mesh.nbtab.size()))) return rc;
+  if ((rc = c->upload(c->d_nbnode, c->mesh.nbnode.data(), c->mesh.nbnode.size()))) return rc;
   if ((rc = c->upload_operators())) return rc;
   if ((rc = c->alloc_shots())) return rc;
   c->have_mesh = true;
@@ -803,13 +779,13 @@ int dgw_set_launch(dgw_ctx *c, int kernel, int elems_per_block, int wgs_per_cu) 
   if (!c) return DGW_EINVAL;
   if (!stage_kernel_supported(kernel, c->R.N, c->precision))
     return c->fail(DGW_EINVAL, "stage kernel not available for this order/precision");
-  c->kernel = kernel;
-  std::vector<int> ch = stage_block_choices(c->R.N, c->precision);
+  std::vector<int> ch = stage_block_choices(kernel, c->R.N, c->precision);
   if (elems_per_block == 0) elems_per_block = ch[0];
   if (std::find(ch.begin(), ch.end(), elems_per_block) == ch.end())
     return c->fail(DGW_EINVAL, "unsupported elements-per-block value");
   if (wgs_per_cu < 0 || wgs_per_cu > 64)
     return c->fail(DGW_EINVAL, "work-groups per CU out of range (0..64)");
+  c->kernel = kernel;
   c->block = elems_per_block;
   c->wpc = wgs_per_cu;
   c->invalidate_graph();

@@ -58,31 +58,6 @@ bool write_cache(const char *path, const std::map<std::string, long> &m) {
   return (bool)f;
 }
 
-template <typename real>
-void fill(dgw_ctx *c, StageArgs<real> &a, void *out, void *res) {
-  a.q_in = (const real *)c->d_q[c->cur];
-  a.q_out = (real *)out;
-  a.res = (real *)res;
-  a.meta = c->d_meta;
-  a.conn = c->d_conn;
-  a.nbtab = c->d_nbtab;
-  a.DrT = (const real *)c->d_DrT;
-  a.DsT = (const real *)c->d_DsT;
-  a.DtT = (const real *)c->d_DtT;
-  a.LIFTT = (const real *)c->d_LIFTT;
-  a.fmask = c->d_fmask;
-  a.K = c->mesh.K;
-  a.shot_stride = c->mesh.K * 9 * c->R.Np;
-  a.shot_step = c->d_step;
-  a.shot_len = c->d_len;
-  a.src_elem = c->d_src_elem;
-  a.src_vec = c->d_src_vec;
-  a.src_par = c->d_src_par;
-  a.rk_a = rk_a()[1];
-  a.rk_b = rk_b()[1];
-  a.rk_c = rk_c()[1];
-  a.dt = c->dt;
-}
 
 }  // namespace
 
@@ -100,7 +75,7 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *kernel,
   std::snprintf(key, sizeof key, "N%d_fp%d_K%lld_S%d", c->R.N, c->precision,
                 (long long)c->mesh.K, c->nshots);
   std::vector<Shape> opts;
-  for (int be : stage_block_choices(c->R.N, c->precision))
+  for (int be : stage_block_choices(0, c->R.N, c->precision))
     for (int w : {0, 2, 4, 8, 16}) opts.push_back({0, be, w});
   auto report = [&](const Shape &o) {
     if (kernel) *kernel = o.kernel;
@@ -139,12 +114,12 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *kernel,
       if (r == 2) (void)hipEventRecord(e0, c->stream);
       if (c->precision == 64) {
         StageArgs<double> a;
-        fill(c, a, out, res);
+        stage_args(c, a, c->d_q[c->cur], out, res, c->d_step, 1);
         err = launch_stage(o.kernel, c->R.N, 64, o.be, o.wpc, c->ncu, c->nshots, &a,
                            c->stream);
       } else {
         StageArgs<float> a;
-        fill(c, a, out, res);
+        stage_args(c, a, c->d_q[c->cur], out, res, c->d_step, 1);
         err = launch_stage(o.kernel, c->R.N, 32, o.be, o.wpc, c->ncu, c->nshots, &a,
                            c->stream);
       }

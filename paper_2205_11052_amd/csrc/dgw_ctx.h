@@ -39,6 +39,7 @@ struct dgw_ctx {
   // device data
   double *d_meta = nullptr;
   int32_t *d_conn = nullptr, *d_nbtab = nullptr, *d_fmask = nullptr;
+  uint8_t *d_nbnode = nullptr;
   void *d_DrT = nullptr, *d_DsT = nullptr, *d_DtT = nullptr, *d_LIFTT = nullptr;
   double *d_M = nullptr;
   void *d_q[2] = {nullptr, nullptr};
@@ -98,3 +99,32 @@ struct dgw_ctx {
   int gather_shots_to_cur(const std::vector<int64_t> &adv);
   void free_adjoint();
 };
+
+// Arguments of one stage launch: state `in` -> `out`, residual `res`, shot
+// step counters `steps`, LSERK stage `stage` (0..4).
+template <typename real>
+inline void stage_args(const dgw_ctx *c, dgw::StageArgs<real> &a, const void *in,
+                       void *out, void *res, const int64_t *steps, int stage) {
+  a.q_in = (const real *)in;
+  a.q_out = (real *)out;
+  a.res = (real *)res;
+  a.meta = c->d_meta;
+  a.conn = c->d_conn;
+  a.nbnode = c->d_nbnode;
+  a.DrT = (const real *)c->d_DrT;
+  a.DsT = (const real *)c->d_DsT;
+  a.DtT = (const real *)c->d_DtT;
+  a.LIFTT = (const real *)c->d_LIFTT;
+  a.fmask = c->d_fmask;
+  a.K = c->mesh.K;
+  a.shot_stride = c->mesh.K * 9 * c->R.Np;
+  a.shot_step = steps;
+  a.shot_len = c->d_len;
+  a.src_elem = c->d_src_elem;
+  a.src_vec = c->d_src_vec;
+  a.src_par = c->d_src_par;
+  a.rk_a = dgw::rk_a()[stage];
+  a.rk_b = dgw::rk_b()[stage];
+  a.rk_c = dgw::rk_c()[stage];
+  a.dt = c->dt;
+}

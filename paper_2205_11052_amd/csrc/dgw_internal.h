@@ -51,6 +51,7 @@ struct MeshData {
   std::vector<int32_t> conn;     // [K][4]
   std::vector<int32_t> nbtab;    // [4][4][6][Nfp] neighbour volume node
   std::vector<int32_t> nbface;   // [4][4][6][Nfp] neighbour face-local node
+  std::vector<uint8_t> nbnode;   // [K][4][Nfp] neighbour volume node (interior faces)
   std::vector<double> volume;    // [K]
   std::vector<double> area;      // [K][4]
 };
@@ -71,7 +72,7 @@ struct StageArgs {
   real *res;
   const double *meta;
   const int32_t *conn;
-  const int32_t *nbtab;
+  const uint8_t *nbnode;        // [K][4 Nfp] neighbour volume node per face node
   const real *DrT, *DsT, *DtT;  // [j][i] (transposed)
   const real *LIFTT;            // [4Nfp][Np] (transposed)
   const int32_t *fmask;         // [4 Nfp]
@@ -136,7 +137,8 @@ hipError_t launch_set_steps(int64_t *steps, int nshots, int64_t value,
                             hipStream_t st);
 
 // Launchers (kernels.hip); return the launch error.
-// kernel 0 (node per thread, LDS tiles): be = elements per work-group,
+// kernel 0 (one thread per element node, 256 threads per work-group): be =
+// elements per work-group,
 // wpc = persistent work-groups per compute unit (0: one work-group per block
 // of elements).  ncu = compute units.
 hipError_t launch_stage(int kernel, int N, int precision, int be, int wpc,
@@ -150,7 +152,7 @@ hipError_t launch_energy(int precision, const void *q, int64_t K, int Np,
 hipError_t launch_finite(int precision, const void *q, int64_t n, int *flag,
                          hipStream_t st);
 // Supported elements-per-block values for an order / precision.
-std::vector<int> stage_block_choices(int N, int precision);
-int default_block(int N, int precision);
+std::vector<int> stage_block_choices(int kernel, int N, int precision);
+int default_block(int kernel, int N, int precision);
 
 }  // namespace dgw

@@ -11,15 +11,20 @@
 // so the one-item form carries no loop.
 //
 // Per item (256 threads):
-//   1. the block's fields q[BE][9][Np] (contiguous in HBM, read once,
-//      coalesced) and its per-element data go to LDS;
-//   2. one thread per (element, face node): own trace from LDS, neighbour
-//      trace from LDS when the neighbour is in the block, else gathered from
-//      L2/HBM through the face-orientation table; exact Riemann flux in jump
-//      form; the nine lifted flux components (times Fscale) go to LDS;
+//   1. every global read of the item's fields is issued at once: the block's
+//      fields q[BE][9][Np] (contiguous in HBM, coalesced) and per-element data
+//      go to LDS, and each thread gathers the neighbour traces of its face
+//      nodes (the neighbour element from the face connectivity, the node from
+//      a per-face-node table, so no load waits on a table lookup) into
+//      registers;
+//   2. one thread per (element, face node): exact Riemann flux in jump form
+//      from the own trace (LDS) and the neighbour's (registers); six lifted
+//      quantities go to LDS: the velocity flux and the velocity change dv,
+//      both times Fscale (the stress flux is lambda (n.dv) I + mu (dv n^T +
+//      n dv^T), n constant per face, so it is formed after lifting dv);
 //   3. one thread per (element, node): reference derivatives of the nine
-//      fields with Dr, Ds, Dt, the physical volume terms, + LIFT . flux, +
-//      point source, then res = a res + dt rhs and q_out = q_in + b res.
+//      fields with Dr, Ds, Dt, the physical volume terms, + the lifted flux,
+//      + point source, then res = a res + dt rhs and q_out = q_in + b res.
 // q_in and q_out are distinct buffers (neighbour traces are read from q_in
 // while other blocks write q_out); res is element-local and updated in place.
 #include <hip/hip_runtime.h>
@@ -59,12 +64,13 @@ __device__ inline int64_t xcd_item(int64_t L, int64_t total) {
 template <int N, typename real, int BE>
 __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t item,
                                            int64_t nblk) {
-  constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Nfp;
+  constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Sz<N>::Nfp;
+  constexpr int FI = (BE * NF + kThreads - 1) / kThreads;   // face items per thread
+  constexpr int UJ = Np % 7 == 0 ? 7 : Np % 5 == 0 ? 5 : 4;  // divides Np
   // declared here (not passed in) so every access stays an LDS access
   __shared__ real sq[BE * 9 * Np];
-  __shared__ real sfl[BE * 9 * NF];
+  __shared__ __attribute__((aligned(16))) real sfl[BE * NF * 6];
   __shared__ double smeta[BE * DGW_META];
-  __shared__ int scn[BE * 4];
   const int shot = (int)(item / nblk);
   const int64_t step = A.shot_step[shot];
   if (step >= A.shot_len[shot]) return;            // uniform per work-group
@@ -78,49 +84,62 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
   real *__restrict__ res = A.res + shot * A.shot_stride;
   const int tid = threadIdx.x;
 
+  // ---- 1. all global reads of the item's fields are issued together ----
   for (int t = tid; t < nE * 9 * Np; t += kThreads) sq[t] = qin[k0 * 9 * Np + t];
   for (int t = tid; t < nE * DGW_META; t += kThreads)
     smeta[t] = A.meta[k0 * DGW_META + t];
-  for (int t = tid; t < nE * 4; t += kThreads) scn[t] = A.conn[k0 * 4 + t];
+  // neighbour traces of this thread's face nodes go to registers
+  real qp[FI][9];
+  int cnv[FI];
+#pragma unroll
+  for (int u = 0; u < FI; ++u) {
+    const int t = tid + u * kThreads;
+    cnv[u] = CONN_ABSORB;
+    if (t < nE * NF) {
+      const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
+      const int64_t k = k0 + e;
+      const int cn = A.conn[k * 4 + f];
+      cnv[u] = cn;
+      if (cn >= 0) {
+        const int64_t base = (int64_t)(cn >> 5) * 9 * Np + A.nbnode[k * NF + fm];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) qp[u][c] = qin[base + c * Np];
+      }
+    }
+  }
   __syncthreads();
 
-  // ---- faces ----------------------------------------------------------
-  for (int t = tid; t < nE * NF; t += kThreads) {
-    const int e = t / NF, fm = t - e * NF, f = fm / Nfp, m = fm - f * Nfp;
+  // ---- 2. faces: exact Riemann flux, six lifted quantities per node ----
+#pragma unroll
+  for (int u = 0; u < FI; ++u) {
+    const int t = tid + u * kThreads;
+    if (t >= nE * NF) continue;
+    const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
     const double *g = smeta + e * DGW_META;
     const real *qe = sq + e * 9 * Np;
     const int n1 = A.fmask[fm];
-    real qm[9], qp[9];
+    real qm[9], p[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) qm[c] = qe[c * Np + n1];
-    const int cn = scn[e * 4 + f];
+    const int cn = cnv[u];
     if (cn >= 0) {
-      const int64_t nb = cn >> 5;
-      const int f2 = (cn >> 3) & 3, o = cn & 7;
-      const int n2 = A.nbtab[((f * 4 + f2) * 6 + o) * Nfp + m];
-      const int64_t le = nb - k0;
-      if (le >= 0 && le < nE) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) qp[c] = sq[le * 9 * Np + c * Np + n2];
-      } else {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) qp[c] = qin[(nb * 9 + c) * Np + n2];
-      }
+      for (int c = 0; c < 9; ++c) p[c] = qp[u][c];
     } else if (cn == CONN_FREE) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) qp[c] = qm[c];
+      for (int c = 0; c < 3; ++c) p[c] = qm[c];
 #pragma unroll
-      for (int c = 3; c < 9; ++c) qp[c] = -qm[c];
+      for (int c = 3; c < 9; ++c) p[c] = -qm[c];
     } else {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) qp[c] = (real)0;
+      for (int c = 0; c < 9; ++c) p[c] = (real)0;
     }
     const real nx = (real)g[M_NORMAL + 3 * f], ny = (real)g[M_NORMAL + 3 * f + 1],
                nz = (real)g[M_NORMAL + 3 * f + 2];
     // jumps [v] = v+ - v-, [t] = (sigma+ - sigma-) n
-    const real dvx = qp[0] - qm[0], dvy = qp[1] - qm[1], dvz = qp[2] - qm[2];
-    const real dsxx = qp[3] - qm[3], dsyy = qp[4] - qm[4], dszz = qp[5] - qm[5];
-    const real dsyz = qp[6] - qm[6], dsxz = qp[7] - qm[7], dsxy = qp[8] - qm[8];
+    const real dvx = p[0] - qm[0], dvy = p[1] - qm[1], dvz = p[2] - qm[2];
+    const real dsxx = p[3] - qm[3], dsyy = p[4] - qm[4], dszz = p[5] - qm[5];
+    const real dsyz = p[6] - qm[6], dsxz = p[7] - qm[7], dsxy = p[8] - qm[8];
     const real dtx = dsxx * nx + dsxy * ny + dsxz * nz;
     const real dty = dsxy * nx + dsyy * ny + dsyz * nz;
     const real dtz = dsxz * nx + dsyz * ny + dszz * nz;
@@ -134,28 +153,21 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
     const real kTx = (dtx - dtn * nx + zsn * (dvx - dvn * nx)) * izs;
     const real kTy = (dty - dtn * ny + zsn * (dvy - dvn * ny)) * izs;
     const real kTz = (dtz - dtn * nz + zsn * (dvz - dvn * nz)) * izs;
-    // dv = v* - v- and dt = t* - t-
-    const real Dvx = kn * nx + kTx, Dvy = kn * ny + kTy, Dvz = kn * nz + kTz;
-    const real ri = (real)g[M_RHOINV], la = (real)g[M_LAM], mu = (real)g[M_MU];
-    const real fs = (real)g[M_FSCALE + f];
-    real fl[9];
-    fl[0] = (zp * kn * nx + zs * kTx) * ri;
-    fl[1] = (zp * kn * ny + zs * kTy) * ri;
-    fl[2] = (zp * kn * nz + zs * kTz) * ri;
-    const real ndv = nx * Dvx + ny * Dvy + nz * Dvz;
-    fl[3] = la * ndv + 2 * mu * Dvx * nx;
-    fl[4] = la * ndv + 2 * mu * Dvy * ny;
-    fl[5] = la * ndv + 2 * mu * Dvz * nz;
-    fl[6] = mu * (Dvy * nz + Dvz * ny);
-    fl[7] = mu * (Dvx * nz + Dvz * nx);
-    fl[8] = mu * (Dvx * ny + Dvy * nx);
-    real *dst = sfl + e * 9 * NF + fm;
-#pragma unroll
-    for (int c = 0; c < 9; ++c) dst[c * NF] = fs * fl[c];
+    const real ri = (real)g[M_RHOINV], fs = (real)g[M_FSCALE + f];
+    // velocity flux (t* - t-)/rho and the velocity change dv = v* - v-; the
+    // stress flux is lambda (n.dv) I + mu (dv n^T + n dv^T) with n constant
+    // on the face, so lifting dv is enough for all six stress components
+    real *d = sfl + (e * NF + fm) * 6;
+    d[0] = fs * (zp * kn * nx + zs * kTx) * ri;
+    d[1] = fs * (zp * kn * ny + zs * kTy) * ri;
+    d[2] = fs * (zp * kn * nz + zs * kTz) * ri;
+    d[3] = fs * (kn * nx + kTx);
+    d[4] = fs * (kn * ny + kTy);
+    d[5] = fs * (kn * nz + kTz);
   }
   __syncthreads();
 
-  // ---- volume + lift + RK update --------------------------------------
+  // ---- 3. volume + lift + RK update: one thread per (element, node) ----
   for (int t = tid; t < nE * Np; t += kThreads) {
     const int e = t / Np, i = t - e * Np;
     const real *qe = sq + e * 9 * Np;
@@ -163,17 +175,32 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
     real dr[9], ds[9], dt[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) dr[c] = ds[c] = dt[c] = (real)0;
-    for (int j = 0; j < Np; ++j) {
-      const real a0 = A.DrT[j * Np + i], a1 = A.DsT[j * Np + i],
-                 a2 = A.DtT[j * Np + i];
+    // column i of the transposed operators, walked in chunks of UJ rows:
+    // inside a chunk every offset is an immediate
+    const real *pr = A.DrT + i, *ps = A.DsT + i, *pt = A.DtT + i;
+    for (int j0 = 0; j0 < Np; j0 += UJ) {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        const real v = qe[c * Np + j];
-        dr[c] += a0 * v;
-        ds[c] += a1 * v;
-        dt[c] += a2 * v;
+      for (int u = 0; u < UJ; ++u) {
+        const real a0 = pr[u * Np], a1 = ps[u * Np], a2 = pt[u * Np];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          const real v = qe[c * Np + j0 + u];
+          dr[c] += a0 * v;
+          ds[c] += a1 * v;
+          dt[c] += a2 * v;
+        }
       }
+      pr += UJ * Np;
+      ps += UJ * Np;
+      pt += UJ * Np;
     }
+    const int64_t k = k0 + e;
+    // the residual loads are issued here, after the volume loop has freed
+    // its registers, so their latency overlaps the lift
+    real rold[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c)
+      rold[c] = (A.rk_a == 0.0) ? (real)0 : res[(k * 9 + c) * Np + i];
     real X[9];
 #pragma unroll
     for (int u = 0; u < 9; ++u) X[u] = (real)g[M_XINV + u];
@@ -193,13 +220,38 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
     rhs[6] = mu * (D(1, 2) + D(2, 1));
     rhs[7] = mu * (D(0, 2) + D(2, 0));
     rhs[8] = mu * (D(0, 1) + D(1, 0));
-    const real *fle = sfl + e * 9 * NF;
-    for (int fm = 0; fm < NF; ++fm) {
-      const real l = A.LIFTT[fm * Np + i];
+    // lift: velocity flux over all faces; lifted dv per face, then the
+    // stress components from it and the face normal
+    const real *fle = sfl + e * NF * 6;
+    const real *pl = A.LIFTT + i;
+    real V0 = 0, V1 = 0, V2 = 0;
+#pragma unroll 1   // unrolled, the persistent form hoists too much and spills
+    for (int f = 0; f < 4; ++f) {
+      real U0 = 0, U1 = 0, U2 = 0;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) rhs[c] += l * fle[c * NF + fm];
+      for (int m = 0; m < Nfp; ++m) {
+        const real l = pl[(f * Nfp + m) * Np];
+        const real *s6 = fle + (f * Nfp + m) * 6;
+        V0 += l * s6[0];
+        V1 += l * s6[1];
+        V2 += l * s6[2];
+        U0 += l * s6[3];
+        U1 += l * s6[4];
+        U2 += l * s6[5];
+      }
+      const real nx = (real)g[M_NORMAL + 3 * f], ny = (real)g[M_NORMAL + 3 * f + 1],
+                 nz = (real)g[M_NORMAL + 3 * f + 2];
+      const real nU = nx * U0 + ny * U1 + nz * U2;
+      rhs[3] += la * nU + 2 * mu * U0 * nx;
+      rhs[4] += la * nU + 2 * mu * U1 * ny;
+      rhs[5] += la * nU + 2 * mu * U2 * nz;
+      rhs[6] += mu * (U1 * nz + U2 * ny);
+      rhs[7] += mu * (U0 * nz + U2 * nx);
+      rhs[8] += mu * (U0 * ny + U1 * nx);
     }
-    const int64_t k = k0 + e;
+    rhs[0] += V0;
+    rhs[1] += V1;
+    rhs[2] += V2;
     if (A.src_elem[shot] == k) {
       const double *sp = A.src_par + 10 * shot;
       const double s = ricker_d(((double)step + A.rk_c) * A.dt, sp[6], sp[7], sp[8]);
@@ -212,7 +264,7 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
     for (int c = 0; c < 9; ++c) {
       const int64_t idx = (k * 9 + c) * Np + i;
       // stage 1 (a = 0) never reads res, so stale values cannot leak in
-      const real r = (A.rk_a == 0.0) ? rdt * rhs[c] : ra * res[idx] + rdt * rhs[c];
+      const real r = (A.rk_a == 0.0) ? rdt * rhs[c] : ra * rold[c] + rdt * rhs[c];
       res[idx] = r;
       qout[idx] = qe[c * Np + i] + rb * r;
     }
@@ -237,15 +289,27 @@ stage_kernel_persistent(StageArgs<real> A, int64_t nblk, int64_t total) {
 }
 
 // elements per work-group: the largest BE with BE * Np <= 256 and the LDS
-// tile (fields, lifted fluxes, per-element data) within 64 KB, and half of it
+// tile (fields, lifted quantities, per-element data) within 64 KB, and half
+// of it
 template <int N, typename real>
 struct Shapes {
   static constexpr int Np = Sz<N>::Np, NF = 4 * Sz<N>::Nfp;
-  static constexpr int per = (9 * Np + 9 * NF) * (int)sizeof(real) + DGW_META * 8 + 16;
+  static constexpr int per = (9 * Np + 6 * NF) * (int)sizeof(real) + DGW_META * 8;
   static constexpr int cap1 = kThreads / Np, cap2 = 65536 / per;
   static constexpr int a = cap1 < cap2 ? cap1 : cap2;
   static constexpr int b = a / 2 > 0 ? a / 2 : 1;
 };
+
+template <int N, typename real, int BE>
+void launch_be(int64_t grid, bool persistent, int64_t nblk, int64_t total,
+               const StageArgs<real> &a, hipStream_t st) {
+  if (persistent)
+    hipLaunchKernelGGL((stage_kernel_persistent<N, real, BE>), dim3((unsigned)grid),
+                       dim3(kThreads), 0, st, a, nblk, total);
+  else
+    hipLaunchKernelGGL((stage_kernel<N, real, BE>), dim3((unsigned)grid), dim3(kThreads),
+                       0, st, a, nblk, total);
+}
 
 template <int N, typename real>
 hipError_t launch_t(int be, int wpc, int ncu, int nshots, const StageArgs<real> &a,
@@ -255,21 +319,12 @@ hipError_t launch_t(int be, int wpc, int ncu, int nshots, const StageArgs<real> 
   const int64_t nblk = (a.K + be - 1) / be;
   const int64_t total = nblk * nshots;
   const int64_t pers = ((int64_t)ncu * wpc + 7) / 8 * 8;
-  if (wpc > 0 && pers < total) {
-    if (be == A_)
-      hipLaunchKernelGGL((stage_kernel_persistent<N, real, A_>), dim3((unsigned)pers),
-                         dim3(kThreads), 0, st, a, nblk, total);
-    else
-      hipLaunchKernelGGL((stage_kernel_persistent<N, real, B_>), dim3((unsigned)pers),
-                         dim3(kThreads), 0, st, a, nblk, total);
-  } else {
-    if (be == A_)
-      hipLaunchKernelGGL((stage_kernel<N, real, A_>), dim3((unsigned)total),
-                         dim3(kThreads), 0, st, a, nblk, total);
-    else
-      hipLaunchKernelGGL((stage_kernel<N, real, B_>), dim3((unsigned)total),
-                         dim3(kThreads), 0, st, a, nblk, total);
-  }
+  const bool persistent = wpc > 0 && pers < total;
+  const int64_t grid = persistent ? pers : total;
+  if (be == A_)
+    launch_be<N, real, A_>(grid, persistent, nblk, total, a, st);
+  else
+    launch_be<N, real, B_>(grid, persistent, nblk, total, a, st);
   return hipGetLastError();
 }
 
@@ -314,12 +369,13 @@ bool stage_kernel_supported(int kernel, int N, int precision) {
   return kernel == 0 && N >= 1 && N <= DGW_MAX_ORDER && (precision == 64 || precision == 32);
 }
 
-std::vector<int> stage_block_choices(int N, int precision) {
+std::vector<int> stage_block_choices(int kernel, int N, int precision) {
+  if (kernel != 0) return {};
   return precision == 64 ? choices_r<double>(N) : choices_r<float>(N);
 }
 
-int default_block(int N, int precision) {
-  std::vector<int> c = stage_block_choices(N, precision);
+int default_block(int kernel, int N, int precision) {
+  std::vector<int> c = stage_block_choices(kernel, N, precision);
   return c.empty() ? 0 : c[0];
 }
 

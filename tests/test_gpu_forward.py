@@ -196,9 +196,10 @@ def test_graph_replay_equals_eager_and_block_shapes_agree():
     for o in outs[1:]:
         assert np.array_equal(outs[0], o)
     # a kernel variant this build does not provide is refused
-    with pytest.raises(DGWError) as ei:
-        s.set_launch(1, 0, 0)
-    assert ei.value.status == "DGW_EINVAL"
+    for bad in ((1, 0, 0), (0, 5, 0), (0, 7, 65)):
+        with pytest.raises(DGWError) as ei:
+            s.set_launch(*bad)
+        assert ei.value.status == "DGW_EINVAL"
 
 
 @pytest.mark.parametrize("precision", [64, 32])
