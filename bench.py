@@ -12,7 +12,10 @@ events.
 Metric: GDOF-stage/s = 9 * Np * K * 5 * steps / seconds / 1e9.
 
 Extra forms reported beside the headline (same GPU, same mesh and medium):
-FP32 fields and arithmetic, and a batch of 32 FP32 shots advanced together.
+FP32 fields and arithmetic (error against the FP64 run stated), a batch of 32
+FP32 shots advanced together, and order 6 in FP64 and FP32.  The adjoint form
+reports seconds per shot of the misfit gradient on the 24576-element order-3
+workload, with its error against central differences measured in the run.
 
 Roofline: the stage kernel's algorithmic HBM bytes per launch (read q and
 res, write res and q', read the per-element data and connectivity) divided by
@@ -25,7 +28,8 @@ CPU baseline: the CPU oracle (plain PyTorch FP64) timed on the host on a
 bounded sample of the same workload (three LSERK4 steps of the full mesh).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--no-forms] [--shape K,E,W] [--copy-probe]
+                       [--no-forms] [--no-adjoint] [--shape K,E,W]
+                       [--copy-probe]
 """
 
 import argparse
@@ -128,6 +132,123 @@ def kernel_avg_ms(s, steps=10):
     return ms, n
 
 
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def adjoint_form(torch, stream, nsteps=1500, ckpt=100, n_fd=2):
+    """Gradient of the receiver misfit with respect to per-element rho,
+    lambda, mu on the 24576-element order-3 workload (layered true medium,
+    blob-perturbed start, dt fixed from the true medium), 1500 steps,
+    checkpoint every 100 steps.  Seconds per shot = forward with checkpoints
+    + reverse sweep, FP64 and FP32; the FP64 gradient is checked live against
+    central differences of the FP64 forward (step 1e-6 relative) on n_fd
+    seeded elements, all three parameters, and the FP32 gradient against the
+    FP64 one."""
+    import workloads as W
+    from paper_2205_11052_amd import Solver
+    wt = W.build_workload("c3_adjoint")
+    ws = W.build_workload("c3_adjoint", medium="blob")
+
+    def make(prec, w, dt=None):
+        s = Solver(w["N"], prec, 1, stream=stream.cuda_stream)
+        s.set_mesh_dict(w["mesh"])
+        s.set_material(w["rho"], w["lam"], w["mu"])
+        s.set_dt(dt if dt is not None else s.suggest_dt(w["cfl"]))
+        s.set_source(0, w["source"], w["f0"], w["t0"], w["amp"])
+        s.set_receivers(0, w["receivers"], nsteps)
+        s.autotune()
+        return s
+
+    with torch.cuda.stream(stream):
+        st = make(64, wt)
+        dt = st.dt
+        st.zero_fields()
+        st.step(nsteps)
+        d = st.read_traces(0)[None]          # observed data [1][R][3][nsteps]
+        st.close()
+        res, grads = {}, {}
+        for prec in (64, 32):
+            s = make(prec, ws, dt)
+            s.zero_fields()
+            s.forward_checkpointed(nsteps, ckpt, d)      # warm-up
+            s.adjoint()
+            s.zero_fields()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mis = s.forward_checkpointed(nsteps, ckpt, d)
+            g = s.adjoint()
+            torch.cuda.synchronize()
+            res["fp%d_s_per_shot" % prec] = round(time.perf_counter() - t0, 4)
+            res["fp%d_misfit" % prec] = float(mis[0])
+            grads[prec] = [x[0] for x in g]
+            if prec == 64:
+                s64 = s
+            else:
+                s.close()
+        g = grads[64]
+        gmax = max(np.abs(x).max() for x in g)
+        eligible = np.nonzero(np.maximum.reduce([np.abs(x) for x in g])
+                              >= 1e-3 * gmax)[0]
+        elems = np.random.default_rng(52).choice(eligible, size=n_fd, replace=False)
+        base = [np.array(ws["rho"]), np.array(ws["lam"]), np.array(ws["mu"])]
+        worst, nfd = 0.0, 0
+        for k in elems:
+            for p in range(3):
+                if abs(g[p][k]) < 1e-3 * gmax:
+                    continue
+                delta = 1e-6 * base[p][k]
+                vals = []
+                for sgn in (1, -1):
+                    m = [b.copy() for b in base]
+                    m[p][k] += sgn * delta
+                    s64.set_material(*m)
+                    s64.zero_fields()
+                    vals.append(s64.forward_checkpointed(nsteps, nsteps, d)[0])
+                fd = (vals[0] - vals[1]) / (2 * delta)
+                worst = max(worst, abs(fd - g[p][k]) / abs(fd))
+                nfd += 1
+        s64.close()
+    res["fd_max_rel_error_fp64"] = worst
+    res["fd_entries"] = nfd
+    res["fp32_grad_rel_l2_vs_fp64"] = rel_l2(np.concatenate(grads[32]),
+                                             np.concatenate(grads[64]))
+    res["workload"] = ("c3_adjoint: 6*16^3 = 24576 tetrahedra, order 3, %d steps, "
+                       "checkpoint every %d, one shot" % (nsteps, ckpt))
+    return res
+
+
+def order6_form(torch, stream, w, steps, warmup):
+    """FP32 and FP64 at order 6 (84 nodes) on the same mesh and medium:
+    throughput, and the FP32 fields' error against the FP64 ones after the
+    same steps."""
+    import workloads as W
+    w6 = W.build_workload("c1_layered_n24", N=6)
+    out = {}
+    fields = {}
+    for prec in (64, 32):
+        with torch.cuda.stream(stream):
+            s = build_solver(w6, prec, stream=stream.cuda_stream)
+            sec, _ = timed_steps(torch, s, stream, steps, warmup)
+            kms, _ = kernel_avg_ms(s)
+            fields[prec] = s.get_fields(0)
+            shape = s.shape
+            s.close()
+        Np = 84
+        out["fp%d" % prec] = {
+            "value": round(9 * Np * w6["K"] * 5 * steps / sec / 1e9, 3),
+            "ms_per_step": round(sec / steps * 1e3, 4),
+            "kernel_avg_ms": round(kms, 5),
+            "hbm_frac": round(stage_bytes(w6["K"], Np, prec // 8) / (kms / 1e3) / 1e9
+                              / HBM_PEAK_GBS, 4),
+            "launch_shape": list(shape)}
+    out["fp32"]["speedup_vs_fp64"] = round(out["fp32"]["value"] / out["fp64"]["value"], 3)
+    out["fp32"]["fields_rel_l2_vs_fp64"] = rel_l2(fields[32], fields[64])
+    return out
+
+
 def cpu_baseline(w, steps=3):
     import torch
     from oracle import solver as O
@@ -156,6 +277,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--shape", default=None,  # kernel,elements,wgs_per_cu
                     help="launch shape 'kernel,elements,wgs_per_cu' (skips the autotuner)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -187,6 +309,7 @@ def main():
         kms, nl = kernel_avg_ms(s)
         s.check_finite()
         shape64 = s.shape
+        q64 = s.get_fields(0) if not args.no_forms else None
     value = dof * 5 * args.steps / sec / 1e9
     bytes_launch = stage_bytes(K, Np, 8)
     achieved = bytes_launch / (kms / 1e3) / 1e9
@@ -219,6 +342,7 @@ def main():
             sec32, _ = timed_steps(torch, s32, stream, args.steps, args.warmup)
             k32, _ = kernel_avg_ms(s32)
             shape32 = s32.shape
+            err32 = rel_l2(s32.get_fields(0), q64)
         del s32
         forms["fp32"] = {
             "value": round(dof * 5 * args.steps / sec32 / 1e9, 3),
@@ -227,7 +351,10 @@ def main():
             "kernel_avg_ms": round(k32, 5),
             "hbm_frac": round(stage_bytes(K, Np, 4) / (k32 / 1e3) / 1e9
                               / HBM_PEAK_GBS, 4),
-            "launch_shape": list(shape32)}
+            "launch_shape": list(shape32),
+            "fields_rel_l2_vs_fp64": err32,
+            "error_note": "final fields after the same %d steps from zero, "
+                          "source active" % (args.warmup + args.steps + 10)}
         pos, lens = W.batched_shots()
         nb = len(pos)
         bsteps = max(10, args.steps // 10)
@@ -250,7 +377,10 @@ def main():
             "launch_shape": list(shapeb),
             "note": "32 shots, one launch per stage over all shots, graph "
                     "replay; lengths 500-2000 steps, all active in the window"}
+        forms["order6"] = order6_form(torch, stream, w, max(20, args.steps // 5), 2)
         out["forms"] = forms
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_form(torch, stream)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
