@@ -159,6 +159,40 @@ int dgw_ctx::upload_operators() {
     if ((rc = upload(d_DtT, c.data(), rs * c.size()))) return rc;
     if ((rc = upload(d_LIFTT, l.data(), rs * l.size()))) return rc;
   }
+  // operator fragments for the matrix-core stage kernel, in MFMA lane
+  // order (lane l of a 16x4 tile holds row l % 16, column l / 16), zero
+  // outside the operator: Avol[a][ks][mt][l] = D_a[16 mt + l % 16][4 ks +
+  // l / 16] and Alift[ks][mt][l] = LIFT[16 mt + l % 16][4 ks + l / 16]
+  {
+    const int MT = (Np + 15) / 16, KS = (Np + 3) / 4, KL = NF / 4;
+    std::vector<double> av((size_t)3 * KS * MT * 64, 0.0), al((size_t)KL * MT * 64, 0.0);
+    const std::vector<double> *D[3] = {&R.Dr, &R.Ds, &R.Dt};
+    for (int a = 0; a < 3; ++a)
+      for (int ks = 0; ks < KS; ++ks)
+        for (int mt = 0; mt < MT; ++mt)
+          for (int l = 0; l < 64; ++l) {
+            const int i = 16 * mt + l % 16, j = 4 * ks + l / 16;
+            if (i < Np && j < Np)
+              av[(((size_t)a * KS + ks) * MT + mt) * 64 + l] = (*D[a])[(size_t)i * Np + j];
+          }
+    for (int ks = 0; ks < KL; ++ks)
+      for (int mt = 0; mt < MT; ++mt)
+        for (int l = 0; l < 64; ++l) {
+          const int i = 16 * mt + l % 16, m = 4 * ks + l / 16;
+          if (i < Np) al[((size_t)ks * MT + mt) * 64 + l] = R.LIFT[(size_t)i * NF + m];
+        }
+    d_Avol = dalloc(rs * av.size());
+    d_Alift = dalloc(rs * al.size());
+    if (!d_Avol || !d_Alift) return fail(DGW_ENOMEM, "device allocation failed (operators)");
+    if (precision == 64) {
+      if ((rc = upload(d_Avol, av.data(), rs * av.size()))) return rc;
+      if ((rc = upload(d_Alift, al.data(), rs * al.size()))) return rc;
+    } else {
+      std::vector<float> avf(av.begin(), av.end()), alf(al.begin(), al.end());
+      if ((rc = upload(d_Avol, avf.data(), rs * avf.size()))) return rc;
+      if ((rc = upload(d_Alift, alf.data(), rs * alf.size()))) return rc;
+    }
+  }
   std::vector<int32_t> fm(R.fmask.begin(), R.fmask.end());
   if ((rc = upload(d_fmask, fm.data(), sizeof(int32_t) * fm.size()))) return rc;
   if ((rc = upload(d_M, R.M.data(), sizeof(double) * R.M.size()))) return rc;

@@ -75,8 +75,9 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *kernel,
   std::snprintf(key, sizeof key, "N%d_fp%d_K%lld_S%d", c->R.N, c->precision,
                 (long long)c->mesh.K, c->nshots);
   std::vector<Shape> opts;
-  for (int be : stage_block_choices(0, c->R.N, c->precision))
-    for (int w : {0, 2, 4, 8, 16}) opts.push_back({0, be, w});
+  for (int kv : {0, 1})
+    for (int be : stage_block_choices(kv, c->R.N, c->precision))
+      for (int w : {0, 2, 4, 8, 16}) opts.push_back({kv, be, w});
   auto report = [&](const Shape &o) {
     if (kernel) *kernel = o.kernel;
     if (elems_per_block) *elems_per_block = o.be;

@@ -41,6 +41,7 @@ struct dgw_ctx {
   int32_t *d_conn = nullptr, *d_nbtab = nullptr, *d_fmask = nullptr;
   uint8_t *d_nbnode = nullptr;
   void *d_DrT = nullptr, *d_DsT = nullptr, *d_DtT = nullptr, *d_LIFTT = nullptr;
+  void *d_Avol = nullptr, *d_Alift = nullptr;   // MFMA operator fragments
   double *d_M = nullptr;
   void *d_q[2] = {nullptr, nullptr};
   void *d_res = nullptr;
@@ -115,6 +116,8 @@ inline void stage_args(const dgw_ctx *c, dgw::StageArgs<real> &a, const void *in
   a.DsT = (const real *)c->d_DsT;
   a.DtT = (const real *)c->d_DtT;
   a.LIFTT = (const real *)c->d_LIFTT;
+  a.Avol = (const real *)c->d_Avol;
+  a.Alift = (const real *)c->d_Alift;
   a.fmask = c->d_fmask;
   a.K = c->mesh.K;
   a.shot_stride = c->mesh.K * 9 * c->R.Np;

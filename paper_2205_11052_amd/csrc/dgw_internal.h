@@ -75,6 +75,10 @@ struct StageArgs {
   const uint8_t *nbnode;        // [K][4 Nfp] neighbour volume node per face node
   const real *DrT, *DsT, *DtT;  // [j][i] (transposed)
   const real *LIFTT;            // [4Nfp][Np] (transposed)
+  // operator fragments in MFMA lane order (stage kernel variant 1):
+  // Avol[a][ks][mt][64] = D_a[16 mt + l % 16][4 ks + l / 16],
+  // Alift[ks][mt][64] = LIFT[16 mt + l % 16][4 ks + l / 16], zero-padded
+  const real *Avol, *Alift;
   const int32_t *fmask;         // [4 Nfp]
   int64_t K;
   int64_t shot_stride;          // K * 9 * Np
@@ -137,8 +141,9 @@ hipError_t launch_set_steps(int64_t *steps, int nshots, int64_t value,
                             hipStream_t st);
 
 // Launchers (kernels.hip); return the launch error.
-// kernel 0 (one thread per element node, 256 threads per work-group): be =
-// elements per work-group,
+// kernel 0 (one thread per element node on the vector ALUs) or 1 (the
+// volume and lift contractions as one GEMM on the matrix cores), both with
+// 256 threads per work-group: be = elements per work-group,
 // wpc = persistent work-groups per compute unit (0: one work-group per block
 // of elements).  ncu = compute units.
 hipError_t launch_stage(int kernel, int N, int precision, int be, int wpc,

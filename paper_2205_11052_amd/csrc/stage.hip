@@ -61,113 +61,178 @@ __device__ inline int64_t xcd_item(int64_t L, int64_t total) {
   return start + (L >> 3);
 }
 
-template <int N, typename real, int BE>
-__device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t item,
-                                           int64_t nblk) {
-  constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Sz<N>::Nfp;
-  constexpr int FI = (BE * NF + kThreads - 1) / kThreads;   // face items per thread
-  constexpr int UJ = Np % 7 == 0 ? 7 : Np % 5 == 0 ? 5 : 4;  // divides Np
-  // declared here (not passed in) so every access stays an LDS access
-  __shared__ real sq[BE * 9 * Np];
-  __shared__ __attribute__((aligned(16))) real sfl[BE * NF * 6];
-  __shared__ double smeta[BE * DGW_META];
-  const int shot = (int)(item / nblk);
-  const int64_t step = A.shot_step[shot];
-  if (step >= A.shot_len[shot]) return;            // uniform per work-group
-  const int64_t k0 = (item - (int64_t)shot * nblk) * BE;
-  // never taken (items cover the mesh exactly), but it bounds nE to
-  // [1, BE] for the compiler, which keeps the register count low
-  if (k0 >= A.K) return;
-  const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
-  const real *__restrict__ qin = A.q_in + shot * A.shot_stride;
-  real *__restrict__ qout = A.q_out + shot * A.shot_stride;
-  real *__restrict__ res = A.res + shot * A.shot_stride;
-  const int tid = threadIdx.x;
+// Matrix-core (MFMA) 16x16x4 tiles.  Lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16] of the 16x4 and 4x16 operands (both precisions); the
+// 16x16 accumulator lives in four registers per lane, lane l holding column
+// l % 16 and, for register r, row 4 (l / 16) + r (FP32) or (l / 16) + 4 r
+// (FP64).  (Layouts checked on the device.)
+template <typename real>
+struct Mma;
+template <>
+struct Mma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static constexpr int row(int g, int r) { return 4 * g + r; }
+};
+template <>
+struct Mma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static constexpr int row(int g, int r) { return g + 4 * r; }
+};
 
-  // ---- 1. all global reads of the item's fields are issued together ----
-  for (int t = tid; t < nE * 9 * Np; t += kThreads) sq[t] = qin[k0 * 9 * Np + t];
-  for (int t = tid; t < nE * DGW_META; t += kThreads)
-    smeta[t] = A.meta[k0 * DGW_META + t];
-  // neighbour traces of this thread's face nodes go to registers
-  real qp[FI][9];
-  int cnv[FI];
+// Phase 3 on the matrix cores.  By linearity the element's metric and
+// material factors move to the input side: every right-hand-side component
+// is rhs_k = sum_a D_a u_{k,a} + LIFT F_k, with u_{k,a} = sum_m c_{k,a,m}
+// q_{f(k,m)} a per-node combination of at most three fields (for example
+// u_{vx,a} = (1/rho) sum_b X^-1[a][b] sigma_{xb} and
+// u_{sxx,a} = (lambda + 2 mu) X^-1[a][0] vx + lambda X^-1[a][1] vy +
+// lambda X^-1[a][2] vz).  So the block's right-hand side is one GEMM,
+// rhs[i][(e,k)] = [Dr Ds Dt LIFT][i][.] x [u_r; u_s; u_t; F][.][(e,k)],
+// whose operator side is shared by all elements: the operator fragments are
+// pre-arranged in HBM in MFMA lane order (L1/L2-resident), the data side is
+// formed in registers from the LDS tile.  Each wave owns 16 columns
+// (element, field); rows are nodes.  The accumulators go through LDS (the
+// flux buffer, dead by then) so that the residual loads, the update and the
+// stores run over the block's contiguous span, fully coalesced.
+template <int N, typename real, int BE>
+__device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real *sq,
+                                            real *sfl, const double *smeta, int nE,
+                                            int64_t k0, int shot, int64_t step,
+                                            real *qout, real *res) {
+  using M = Mma<real>;
+  using v4 = typename M::v4;
+  constexpr int Np = Sz<N>::Np, NF = 4 * Sz<N>::Nfp;
+  constexpr int MT = (Np + 15) / 16;        // row tiles of 16 nodes
+  constexpr int KS = (Np + 3) / 4;          // k-steps per reference direction
+  constexpr int KL = NF / 4;                // k-steps of the lift (4 Nfp % 4 == 0)
+  constexpr int NT = (9 * BE + 15) / 16;    // column tiles
+  constexpr int UP = (BE * 9 * Np + kThreads - 1) / kThreads;  // update items
+  static_assert(9 * Np <= 9 * NF, "the flux buffer holds the right-hand side");
+  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4;
+  const int span = nE * 9 * Np;
+  const bool first = A.rk_a == 0.0;
+  // residual loads of this thread's update items, issued first
+  real rold[UP];
 #pragma unroll
-  for (int u = 0; u < FI; ++u) {
+  for (int u = 0; u < UP; ++u) {
     const int t = tid + u * kThreads;
-    cnv[u] = CONN_ABSORB;
-    if (t < nE * NF) {
-      const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
-      const int64_t k = k0 + e;
-      const int cn = A.conn[k * 4 + f];
-      cnv[u] = cn;
-      if (cn >= 0) {
-        const int64_t base = (int64_t)(cn >> 5) * 9 * Np + A.nbnode[k * NF + fm];
+    rold[u] = (!first && t < span) ? res[k0 * 9 * Np + t] : (real)0;
+  }
+  v4 acc[NT > 4 ? 2 : 1][MT];
+  int ntl = 0;
+  for (int nt = tid >> 6; nt < NT; nt += kThreads / 64, ++ntl) {
+    const int col = nt * 16 + (lane & 15);
+    const bool cok = col < 9 * nE;
+    const int e = cok ? col / 9 : 0, k = cok ? col - 9 * (col / 9) : 0;
+    const real *qe = sq + e * 9 * Np;
+    const double *gm = smeta + e * DGW_META;
+    // input-side coefficients of this column
+    real X[9];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) qp[u][c] = qin[base + c * Np];
+    for (int u = 0; u < 9; ++u) X[u] = (real)gm[M_XINV + u];
+    const real ri = (real)gm[M_RHOINV], la = (real)gm[M_LAM], mu = (real)gm[M_MU];
+    const real l2 = la + 2 * mu;
+    int f0, f1, f2;
+    real c[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const real x0 = X[3 * a], x1 = X[3 * a + 1], x2 = X[3 * a + 2];
+      switch (k) {
+        case 0: case 1: case 2:
+          c[a][0] = ri * x0; c[a][1] = ri * x1; c[a][2] = ri * x2; break;
+        case 3: c[a][0] = l2 * x0; c[a][1] = la * x1; c[a][2] = la * x2; break;
+        case 4: c[a][0] = la * x0; c[a][1] = l2 * x1; c[a][2] = la * x2; break;
+        case 5: c[a][0] = la * x0; c[a][1] = la * x1; c[a][2] = l2 * x2; break;
+        case 6: c[a][0] = mu * x2; c[a][1] = mu * x1; c[a][2] = 0; break;
+        case 7: c[a][0] = mu * x2; c[a][1] = mu * x0; c[a][2] = 0; break;
+        default: c[a][0] = mu * x1; c[a][1] = mu * x0; c[a][2] = 0; break;
       }
     }
-  }
-  __syncthreads();
-
-  // ---- 2. faces: exact Riemann flux, six lifted quantities per node ----
-#pragma unroll
-  for (int u = 0; u < FI; ++u) {
-    const int t = tid + u * kThreads;
-    if (t >= nE * NF) continue;
-    const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
-    const double *g = smeta + e * DGW_META;
-    const real *qe = sq + e * 9 * Np;
-    const int n1 = A.fmask[fm];
-    real qm[9], p[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) qm[c] = qe[c * Np + n1];
-    const int cn = cnv[u];
-    if (cn >= 0) {
-#pragma unroll
-      for (int c = 0; c < 9; ++c) p[c] = qp[u][c];
-    } else if (cn == CONN_FREE) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) p[c] = qm[c];
-#pragma unroll
-      for (int c = 3; c < 9; ++c) p[c] = -qm[c];
-    } else {
-#pragma unroll
-      for (int c = 0; c < 9; ++c) p[c] = (real)0;
+    // fields combined for each right-hand-side component (x, y, z parts)
+    switch (k) {
+      case 0: f0 = 3; f1 = 8; f2 = 7; break;   // (sxx, sxy, sxz)
+      case 1: f0 = 8; f1 = 4; f2 = 6; break;   // (sxy, syy, syz)
+      case 2: f0 = 7; f1 = 6; f2 = 5; break;   // (sxz, syz, szz)
+      case 6: f0 = 1; f1 = 2; f2 = 0; break;   // (vy, vz)
+      case 7: f0 = 0; f1 = 2; f2 = 1; break;   // (vx, vz)
+      default: f0 = 0; f1 = 1; f2 = 2; break;  // (vx, vy, vz)
     }
-    const real nx = (real)g[M_NORMAL + 3 * f], ny = (real)g[M_NORMAL + 3 * f + 1],
-               nz = (real)g[M_NORMAL + 3 * f + 2];
-    // jumps [v] = v+ - v-, [t] = (sigma+ - sigma-) n
-    const real dvx = p[0] - qm[0], dvy = p[1] - qm[1], dvz = p[2] - qm[2];
-    const real dsxx = p[3] - qm[3], dsyy = p[4] - qm[4], dszz = p[5] - qm[5];
-    const real dsyz = p[6] - qm[6], dsxz = p[7] - qm[7], dsxy = p[8] - qm[8];
-    const real dtx = dsxx * nx + dsxy * ny + dsxz * nz;
-    const real dty = dsxy * nx + dsyy * ny + dsyz * nz;
-    const real dtz = dsxz * nx + dsyz * ny + dszz * nz;
-    const real dvn = dvx * nx + dvy * ny + dvz * nz;
-    const real dtn = dtx * nx + dty * ny + dtz * nz;
-    const real zp = (real)g[M_ZP], zs = (real)g[M_ZS];
-    const real zpn = (real)g[M_ZPNB + f], zsn = (real)g[M_ZSNB + f];
-    const real izp = (real)g[M_IZPS + f], izs = (real)g[M_IZSS + f];
-    // normal and tangential Riemann amplitudes
-    const real kn = (dtn + zpn * dvn) * izp;
-    const real kTx = (dtx - dtn * nx + zsn * (dvx - dvn * nx)) * izs;
-    const real kTy = (dty - dtn * ny + zsn * (dvy - dvn * ny)) * izs;
-    const real kTz = (dtz - dtn * nz + zsn * (dvz - dvn * nz)) * izs;
-    const real ri = (real)g[M_RHOINV], fs = (real)g[M_FSCALE + f];
-    // velocity flux (t* - t-)/rho and the velocity change dv = v* - v-; the
-    // stress flux is lambda (n.dv) I + mu (dv n^T + n dv^T) with n constant
-    // on the face, so lifting dv is enough for all six stress components
-    real *d = sfl + (e * NF + fm) * 6;
-    d[0] = fs * (zp * kn * nx + zs * kTx) * ri;
-    d[1] = fs * (zp * kn * ny + zs * kTy) * ri;
-    d[2] = fs * (zp * kn * nz + zs * kTz) * ri;
-    d[3] = fs * (kn * nx + kTx);
-    d[4] = fs * (kn * ny + kTy);
-    d[5] = fs * (kn * nz + kTz);
+    const real *q0 = qe + f0 * Np, *q1 = qe + f1 * Np, *q2 = qe + f2 * Np;
+    v4 *ac = acc[ntl];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) ac[mt] = v4{0, 0, 0, 0};
+    // volume: three reference directions, K = Np (padded to a multiple of 4)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const real ca0 = c[a][0], ca1 = c[a][1], ca2 = c[a][2];
+      const real *Ab = A.Avol + (size_t)a * KS * MT * 64 + lane;
+      for (int ks = 0; ks < KS; ++ks) {
+        const int j = 4 * ks + g;
+        real b = 0;
+        if (j < Np) b = ca0 * q0[j] + ca1 * q1[j] + ca2 * q2[j];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) ac[mt] = M::mma(Ab[(ks * MT + mt) * 64], b, ac[mt]);
+      }
+    }
+    // lift: the column's flux on the 4 Nfp face nodes
+    const real *fl = sfl + (e * 9 + k) * NF;
+    const real *Al = A.Alift + lane;
+    for (int ks = 0; ks < KL; ++ks) {
+      const real b = fl[4 * ks + g];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) ac[mt] = M::mma(Al[(ks * MT + mt) * 64], b, ac[mt]);
+    }
+  }
+  __syncthreads();   // every wave is done with the flux buffer
+  // right-hand side to LDS in the block's (element, field, node) order
+  ntl = 0;
+  for (int nt = tid >> 6; nt < NT; nt += kThreads / 64, ++ntl) {
+    const int col = nt * 16 + (lane & 15);
+    if (col < 9 * nE) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * mt + M::row(g, r);
+          if (i < Np) sfl[col * Np + i] = acc[ntl][mt][r];
+        }
+    }
   }
   __syncthreads();
+  // point source and LSERK update over the contiguous span
+  const real ra = (real)A.rk_a, rb = (real)A.rk_b, rdt = (real)A.dt;
+  const int64_t es = (int64_t)A.src_elem[shot] - k0;   // source element in block
+  double s = 0.0;
+  const double *sp = A.src_par + 10 * shot;
+  if (es >= 0 && es < nE) s = ricker_d(((double)step + A.rk_c) * A.dt, sp[6], sp[7], sp[8]);
+  real *qo = qout + k0 * 9 * Np, *rs = res + k0 * 9 * Np;
+#pragma unroll
+  for (int u = 0; u < UP; ++u) {
+    const int t = tid + u * kThreads;
+    if (t >= span) continue;
+    real rhs = sfl[t];
+    const int e = t / (9 * Np), ci = t - e * 9 * Np, c = ci / Np, i = ci - c * Np;
+    if (e == es && c >= 3) rhs += (real)(s * sp[c - 3] * A.src_vec[shot * Np + i]);
+    const real rn = first ? rdt * rhs : ra * rold[u] + rdt * rhs;
+    rs[t] = rn;
+    qo[t] = sq[t] + rb * rn;
+  }
+}
 
-  // ---- 3. volume + lift + RK update: one thread per (element, node) ----
+// Phase 3 on the vector ALUs: one thread per (element, node).
+template <int N, typename real, int BE>
+__device__ __forceinline__ void phase3_nodes(const StageArgs<real> &A, const real *sq,
+                                             const real *sfl, const double *smeta,
+                                             int nE, int64_t k0, int shot, int64_t step,
+                                             real *qout, real *res) {
+  constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Sz<N>::Nfp;
+  constexpr int UJ = Np % 7 == 0 ? 7 : Np % 5 == 0 ? 5 : 4;  // divides Np
+  const int tid = threadIdx.x;
   for (int t = tid; t < nE * Np; t += kThreads) {
     const int e = t / Np, i = t - e * Np;
     const real *qe = sq + e * 9 * Np;
@@ -178,6 +243,7 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
     // column i of the transposed operators, walked in chunks of UJ rows:
     // inside a chunk every offset is an immediate
     const real *pr = A.DrT + i, *ps = A.DsT + i, *pt = A.DtT + i;
+#pragma unroll 1   // a short chunk loop unrolled would hoist every load
     for (int j0 = 0; j0 < Np; j0 += UJ) {
 #pragma unroll
       for (int u = 0; u < UJ; ++u) {
@@ -271,87 +337,221 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
   }
 }
 
+template <int N, typename real, int BE, int V>
+__device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t item,
+                                           int64_t nblk) {
+  constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Sz<N>::Nfp;
+  constexpr int FI = (BE * NF + kThreads - 1) / kThreads;   // face items per thread
+  // declared here (not passed in) so every access stays an LDS access
+  __shared__ real sq[BE * 9 * Np];
+  __shared__ __attribute__((aligned(16))) real sfl[BE * NF * (V == 0 ? 6 : 9)];
+  __shared__ double smeta[BE * DGW_META];
+  const int shot = (int)(item / nblk);
+  const int64_t step = A.shot_step[shot];
+  if (step >= A.shot_len[shot]) return;            // uniform per work-group
+  const int64_t k0 = (item - (int64_t)shot * nblk) * BE;
+  // never taken (items cover the mesh exactly), but it bounds nE to
+  // [1, BE] for the compiler, which keeps the register count low
+  if (k0 >= A.K) return;
+  const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
+  const real *__restrict__ qin = A.q_in + shot * A.shot_stride;
+  real *__restrict__ qout = A.q_out + shot * A.shot_stride;
+  real *__restrict__ res = A.res + shot * A.shot_stride;
+  const int tid = threadIdx.x;
+
+  // ---- 1. all global reads of the item's fields are issued together ----
+  for (int t = tid; t < nE * 9 * Np; t += kThreads) sq[t] = qin[k0 * 9 * Np + t];
+  for (int t = tid; t < nE * DGW_META; t += kThreads)
+    smeta[t] = A.meta[k0 * DGW_META + t];
+  // neighbour traces of this thread's face nodes go to registers
+  real qp[FI][9];
+  int cnv[FI];
+#pragma unroll
+  for (int u = 0; u < FI; ++u) {
+    const int t = tid + u * kThreads;
+    cnv[u] = CONN_ABSORB;
+    if (t < nE * NF) {
+      const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
+      const int64_t k = k0 + e;
+      const int cn = A.conn[k * 4 + f];
+      cnv[u] = cn;
+      if (cn >= 0) {
+        const int64_t base = (int64_t)(cn >> 5) * 9 * Np + A.nbnode[k * NF + fm];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) qp[u][c] = qin[base + c * Np];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 2. faces: exact Riemann flux, six lifted quantities per node ----
+#pragma unroll
+  for (int u = 0; u < FI; ++u) {
+    const int t = tid + u * kThreads;
+    if (t >= nE * NF) continue;
+    const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
+    const double *g = smeta + e * DGW_META;
+    const real *qe = sq + e * 9 * Np;
+    const int n1 = A.fmask[fm];
+    real qm[9], p[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) qm[c] = qe[c * Np + n1];
+    const int cn = cnv[u];
+    if (cn >= 0) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) p[c] = qp[u][c];
+    } else if (cn == CONN_FREE) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p[c] = qm[c];
+#pragma unroll
+      for (int c = 3; c < 9; ++c) p[c] = -qm[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) p[c] = (real)0;
+    }
+    const real nx = (real)g[M_NORMAL + 3 * f], ny = (real)g[M_NORMAL + 3 * f + 1],
+               nz = (real)g[M_NORMAL + 3 * f + 2];
+    // jumps [v] = v+ - v-, [t] = (sigma+ - sigma-) n
+    const real dvx = p[0] - qm[0], dvy = p[1] - qm[1], dvz = p[2] - qm[2];
+    const real dsxx = p[3] - qm[3], dsyy = p[4] - qm[4], dszz = p[5] - qm[5];
+    const real dsyz = p[6] - qm[6], dsxz = p[7] - qm[7], dsxy = p[8] - qm[8];
+    const real dtx = dsxx * nx + dsxy * ny + dsxz * nz;
+    const real dty = dsxy * nx + dsyy * ny + dsyz * nz;
+    const real dtz = dsxz * nx + dsyz * ny + dszz * nz;
+    const real dvn = dvx * nx + dvy * ny + dvz * nz;
+    const real dtn = dtx * nx + dty * ny + dtz * nz;
+    const real zp = (real)g[M_ZP], zs = (real)g[M_ZS];
+    const real zpn = (real)g[M_ZPNB + f], zsn = (real)g[M_ZSNB + f];
+    const real izp = (real)g[M_IZPS + f], izs = (real)g[M_IZSS + f];
+    // normal and tangential Riemann amplitudes
+    const real kn = (dtn + zpn * dvn) * izp;
+    const real kTx = (dtx - dtn * nx + zsn * (dvx - dvn * nx)) * izs;
+    const real kTy = (dty - dtn * ny + zsn * (dvy - dvn * ny)) * izs;
+    const real kTz = (dtz - dtn * nz + zsn * (dvz - dvn * nz)) * izs;
+    const real ri = (real)g[M_RHOINV], fs = (real)g[M_FSCALE + f];
+    // velocity flux (t* - t-)/rho and the velocity change dv = v* - v-; the
+    // stress flux is lambda (n.dv) I + mu (dv n^T + n dv^T) with n constant
+    // on the face, so lifting dv is enough for all six stress components
+    if constexpr (V == 0) {
+      real *d = sfl + (e * NF + fm) * 6;
+      d[0] = fs * (zp * kn * nx + zs * kTx) * ri;
+      d[1] = fs * (zp * kn * ny + zs * kTy) * ri;
+      d[2] = fs * (zp * kn * nz + zs * kTz) * ri;
+      d[3] = fs * (kn * nx + kTx);
+      d[4] = fs * (kn * ny + kTy);
+      d[5] = fs * (kn * nz + kTz);
+    } else {
+      // all nine lifted components, field-major (the GEMM's data side)
+      const real la = (real)g[M_LAM], mu = (real)g[M_MU];
+      const real Dvx = fs * (kn * nx + kTx), Dvy = fs * (kn * ny + kTy),
+                 Dvz = fs * (kn * nz + kTz);
+      const real ndv = nx * Dvx + ny * Dvy + nz * Dvz;
+      real *d = sfl + e * 9 * NF + fm;
+      d[0 * NF] = fs * (zp * kn * nx + zs * kTx) * ri;
+      d[1 * NF] = fs * (zp * kn * ny + zs * kTy) * ri;
+      d[2 * NF] = fs * (zp * kn * nz + zs * kTz) * ri;
+      d[3 * NF] = la * ndv + 2 * mu * Dvx * nx;
+      d[4 * NF] = la * ndv + 2 * mu * Dvy * ny;
+      d[5 * NF] = la * ndv + 2 * mu * Dvz * nz;
+      d[6 * NF] = mu * (Dvy * nz + Dvz * ny);
+      d[7 * NF] = mu * (Dvx * nz + Dvz * nx);
+      d[8 * NF] = mu * (Dvx * ny + Dvy * nx);
+    }
+  }
+  __syncthreads();
+
+
+  if constexpr (V == 1)
+    phase3_mfma<N, real, BE>(A, sq, sfl, smeta, nE, k0, shot, step, qout, res);
+  else
+    phase3_nodes<N, real, BE>(A, sq, sfl, smeta, nE, k0, shot, step, qout, res);
+}
+
 // One work-group per item.
-template <int N, typename real, int BE>
+template <int N, typename real, int BE, int V>
 __global__ void __launch_bounds__(kThreads)
 stage_kernel(StageArgs<real> A, int64_t nblk, int64_t total) {
-  stage_item<N, real, BE>(A, xcd_item(blockIdx.x, total), nblk);
+  stage_item<N, real, BE, V>(A, xcd_item(blockIdx.x, total), nblk);
 }
 
 // Persistent grid (a multiple of 8 work-groups) looping over the items.
-template <int N, typename real, int BE>
+template <int N, typename real, int BE, int V>
 __global__ void __launch_bounds__(kThreads)
 stage_kernel_persistent(StageArgs<real> A, int64_t nblk, int64_t total) {
   for (int64_t L = blockIdx.x; L < total; L += gridDim.x) {
-    stage_item<N, real, BE>(A, xcd_item(L, total), nblk);
+    stage_item<N, real, BE, V>(A, xcd_item(L, total), nblk);
     __syncthreads();   // LDS is reused by the next item
   }
 }
 
-// elements per work-group: the largest BE with BE * Np <= 256 and the LDS
-// tile (fields, lifted quantities, per-element data) within 64 KB, and half
-// of it
-template <int N, typename real>
+// Elements per work-group for variant V: the largest BE with one thread per
+// element node (V = 0: BE * Np <= 256) or one MFMA column per (element,
+// field) (V = 1: 9 BE <= 64, four waves of 16 columns), with the LDS tile
+// (fields, lifted flux, per-element data) within 64 KB; and half of it.
+template <int N, typename real, int V>
 struct Shapes {
   static constexpr int Np = Sz<N>::Np, NF = 4 * Sz<N>::Nfp;
-  static constexpr int per = (9 * Np + 6 * NF) * (int)sizeof(real) + DGW_META * 8;
-  static constexpr int cap1 = kThreads / Np, cap2 = 65536 / per;
+  static constexpr int per =
+      (9 * Np + (V == 0 ? 6 : 9) * NF) * (int)sizeof(real) + DGW_META * 8;
+  static constexpr int cap1 = V == 0 ? kThreads / Np : kThreads / 64 * 16 / 9;
+  static constexpr int cap2 = 65536 / per;
   static constexpr int a = cap1 < cap2 ? cap1 : cap2;
   static constexpr int b = a / 2 > 0 ? a / 2 : 1;
 };
 
-template <int N, typename real, int BE>
+template <int N, typename real, int BE, int V>
 void launch_be(int64_t grid, bool persistent, int64_t nblk, int64_t total,
                const StageArgs<real> &a, hipStream_t st) {
   if (persistent)
-    hipLaunchKernelGGL((stage_kernel_persistent<N, real, BE>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((stage_kernel_persistent<N, real, BE, V>), dim3((unsigned)grid),
                        dim3(kThreads), 0, st, a, nblk, total);
   else
-    hipLaunchKernelGGL((stage_kernel<N, real, BE>), dim3((unsigned)grid), dim3(kThreads),
-                       0, st, a, nblk, total);
+    hipLaunchKernelGGL((stage_kernel<N, real, BE, V>), dim3((unsigned)grid),
+                       dim3(kThreads), 0, st, a, nblk, total);
 }
 
-template <int N, typename real>
+template <int N, typename real, int V>
 hipError_t launch_t(int be, int wpc, int ncu, int nshots, const StageArgs<real> &a,
                     hipStream_t st) {
-  constexpr int A_ = Shapes<N, real>::a, B_ = Shapes<N, real>::b;
+  constexpr int A_ = Shapes<N, real, V>::a, B_ = Shapes<N, real, V>::b;
   if (be != A_ && be != B_) return hipErrorInvalidValue;
+  if (V == 1 && (a.Avol == nullptr || a.Alift == nullptr)) return hipErrorInvalidValue;
   const int64_t nblk = (a.K + be - 1) / be;
   const int64_t total = nblk * nshots;
   const int64_t pers = ((int64_t)ncu * wpc + 7) / 8 * 8;
   const bool persistent = wpc > 0 && pers < total;
   const int64_t grid = persistent ? pers : total;
   if (be == A_)
-    launch_be<N, real, A_>(grid, persistent, nblk, total, a, st);
+    launch_be<N, real, A_, V>(grid, persistent, nblk, total, a, st);
   else
-    launch_be<N, real, B_>(grid, persistent, nblk, total, a, st);
+    launch_be<N, real, B_, V>(grid, persistent, nblk, total, a, st);
   return hipGetLastError();
 }
 
-template <typename real>
+template <typename real, int V>
 hipError_t launch_r(int N, int be, int wpc, int ncu, int nshots, const void *args,
                     hipStream_t st) {
   const StageArgs<real> &a = *(const StageArgs<real> *)args;
   switch (N) {
-    case 1: return launch_t<1, real>(be, wpc, ncu, nshots, a, st);
-    case 2: return launch_t<2, real>(be, wpc, ncu, nshots, a, st);
-    case 3: return launch_t<3, real>(be, wpc, ncu, nshots, a, st);
-    case 4: return launch_t<4, real>(be, wpc, ncu, nshots, a, st);
-    case 5: return launch_t<5, real>(be, wpc, ncu, nshots, a, st);
-    case 6: return launch_t<6, real>(be, wpc, ncu, nshots, a, st);
+    case 1: return launch_t<1, real, V>(be, wpc, ncu, nshots, a, st);
+    case 2: return launch_t<2, real, V>(be, wpc, ncu, nshots, a, st);
+    case 3: return launch_t<3, real, V>(be, wpc, ncu, nshots, a, st);
+    case 4: return launch_t<4, real, V>(be, wpc, ncu, nshots, a, st);
+    case 5: return launch_t<5, real, V>(be, wpc, ncu, nshots, a, st);
+    case 6: return launch_t<6, real, V>(be, wpc, ncu, nshots, a, st);
   }
   return hipErrorInvalidValue;
 }
 
-template <typename real>
+template <typename real, int V>
 std::vector<int> choices_r(int N) {
   switch (N) {
-    case 1: return {Shapes<1, real>::a, Shapes<1, real>::b};
-    case 2: return {Shapes<2, real>::a, Shapes<2, real>::b};
-    case 3: return {Shapes<3, real>::a, Shapes<3, real>::b};
-    case 4: return {Shapes<4, real>::a, Shapes<4, real>::b};
-    case 5: return {Shapes<5, real>::a, Shapes<5, real>::b};
-    case 6: return {Shapes<6, real>::a, Shapes<6, real>::b};
+    case 1: return {Shapes<1, real, V>::a, Shapes<1, real, V>::b};
+    case 2: return {Shapes<2, real, V>::a, Shapes<2, real, V>::b};
+    case 3: return {Shapes<3, real, V>::a, Shapes<3, real, V>::b};
+    case 4: return {Shapes<4, real, V>::a, Shapes<4, real, V>::b};
+    case 5: return {Shapes<5, real, V>::a, Shapes<5, real, V>::b};
+    case 6: return {Shapes<6, real, V>::a, Shapes<6, real, V>::b};
   }
   return {};
 }
@@ -361,17 +561,22 @@ std::vector<int> choices_r(int N) {
 hipError_t launch_stage(int kernel, int N, int precision, int be, int wpc, int ncu,
                         int nshots, const void *args, hipStream_t st) {
   if (!stage_kernel_supported(kernel, N, precision)) return hipErrorInvalidValue;
-  if (precision == 64) return launch_r<double>(N, be, wpc, ncu, nshots, args, st);
-  return launch_r<float>(N, be, wpc, ncu, nshots, args, st);
+  if (precision == 64)
+    return kernel == 0 ? launch_r<double, 0>(N, be, wpc, ncu, nshots, args, st)
+                       : launch_r<double, 1>(N, be, wpc, ncu, nshots, args, st);
+  return kernel == 0 ? launch_r<float, 0>(N, be, wpc, ncu, nshots, args, st)
+                     : launch_r<float, 1>(N, be, wpc, ncu, nshots, args, st);
 }
 
 bool stage_kernel_supported(int kernel, int N, int precision) {
-  return kernel == 0 && N >= 1 && N <= DGW_MAX_ORDER && (precision == 64 || precision == 32);
+  return (kernel == 0 || kernel == 1) && N >= 1 && N <= DGW_MAX_ORDER &&
+         (precision == 64 || precision == 32);
 }
 
 std::vector<int> stage_block_choices(int kernel, int N, int precision) {
-  if (kernel != 0) return {};
-  return precision == 64 ? choices_r<double>(N) : choices_r<float>(N);
+  if (kernel == 1) return precision == 64 ? choices_r<double, 1>(N) : choices_r<float, 1>(N);
+  if (kernel == 0) return precision == 64 ? choices_r<double, 0>(N) : choices_r<float, 0>(N);
+  return {};
 }
 
 int default_block(int kernel, int N, int precision) {

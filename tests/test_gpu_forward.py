@@ -51,12 +51,17 @@ def test_c0_periodic_plane_wave_fp64():
     s.check_finite()
 
 
-@pytest.mark.parametrize("N", range(1, 7))
-def test_all_orders_all_boundaries_fp64(N):
+# stage kernel variants: 0 = one thread per node on the vector ALUs,
+# 1 = volume and lift as one GEMM on the matrix cores
+KERNELS = (0, 1)
+
+
+@pytest.mark.parametrize("N,kernel", [(N, kv) for kv in KERNELS for N in range(1, 7)])
+def test_all_orders_all_boundaries_fp64(N, kernel):
     mesh = W.kuhn_cube(2, 1.0)          # free-surface top, absorbing sides
     K = mesh["etov"].shape[0]
     rho, lam, mu = _random_medium(K, 100 + N)
-    say("case orders fp64 N=%d K=%d" % (N, K))
+    say("case orders fp64 N=%d K=%d kernel=%d" % (N, K, kernel))
     P = oracle_problem(mesh, N)
     dt = P.suggest_dt(rho, lam, mu, 0.5)
     q0 = random_fields(K, P.Np, 200 + N)
@@ -65,7 +70,7 @@ def test_all_orders_all_boundaries_fp64(N):
     rec = np.array([[0.2, 0.3, 1.0], [0.8, 0.6, 0.5], [0.1, 0.9, 0.0]])
     P.set_source(src, 3.0, 0.1, 2.0, moment=moment)
     P.set_receivers(rec)
-    s = gpu_solver(mesh, N, rho, lam, mu, dt)
+    s = gpu_solver(mesh, N, rho, lam, mu, dt, kernel=kernel)
     s.set_source(0, src, 3.0, 0.1, 2.0, moment=moment)
     s.set_receivers(0, rec, 16)
     s.set_fields(0, q0)
@@ -121,7 +126,8 @@ def test_full_size_layered_fp64_bench_launch():
     q0 = random_fields(w["K"], P.Np, 7)
     q_ora, tr_ora = oracle_run(P, q0, w["rho"], w["lam"], w["mu"], dt, 2,
                                record=True)
-    shapes = [(0, be, wpc) for be in (7, 3) for wpc in (0, 2, 4, 8, 16)]
+    shapes = [(kv, be, wpc) for kv in KERNELS for be in (7, 3)
+              for wpc in (0, 2, 4, 8, 16)]
     s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
     s.set_source(0, w["source"], w["f0"], 0.05, w["amp"])
     s.set_receivers(0, w["receivers"], 8)
@@ -135,12 +141,14 @@ def test_full_size_layered_fp64_bench_launch():
         assert err <= FP64_TOL and terr <= FP64_TOL
 
 
-def test_fp32_error_against_fp64_oracle():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_fp32_error_against_fp64_oracle(kernel):
     w = W.build_workload("c0_periodic_pwave")
-    say("case c0 fp32")
+    say("case c0 fp32 kernel=%d" % kernel)
     P = oracle_problem(w["mesh"], w["N"])
     dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
-    s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt, 32)
+    s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt, 32,
+                   kernel=kernel)
     s.set_fields(0, w["q0"])
     s.step(w["steps"])
     q_ora, _ = oracle_run(P, w["q0"], w["rho"], w["lam"], w["mu"], dt,
@@ -150,17 +158,18 @@ def test_fp32_error_against_fp64_oracle():
     assert err <= FP32_TOL
 
 
-@pytest.mark.parametrize("N", [4, 6])
-def test_fp32_reduced_layered(N):
+@pytest.mark.parametrize("N,kernel", [(N, kv) for kv in KERNELS for N in (4, 6)])
+def test_fp32_reduced_layered(N, kernel):
     w = _reduced_c1(n=4, N=N)
-    say("case reduced c2 fp32 N=%d K=%d" % (N, w["K"]))
+    say("case reduced c2 fp32 N=%d K=%d kernel=%d" % (N, w["K"], kernel))
     P = oracle_problem(w["mesh"], w["N"])
     dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
     P.set_source(w["source"], w["f0"], w["t0"], w["amp"])
     P.set_receivers(w["receivers"])
     q0 = random_fields(w["K"], P.Np, 31)
     nst = 10
-    s = gpu_solver(w["mesh"], N, w["rho"], w["lam"], w["mu"], dt, 32)
+    s = gpu_solver(w["mesh"], N, w["rho"], w["lam"], w["mu"], dt, 32,
+                   kernel=kernel)
     s.set_source(0, w["source"], w["f0"], w["t0"], w["amp"])
     s.set_receivers(0, w["receivers"], nst)
     s.set_fields(0, q0)
@@ -182,6 +191,7 @@ def test_graph_replay_equals_eager_and_block_shapes_agree():
     outs = []
     shapes = ((False, 0, 0, 0), (True, 0, 0, 0), (False, 0, 3, 0),
               (False, 0, 7, 4), (False, 0, 3, 1))
+    mma_shapes = ((False, 1, 0, 0), (True, 1, 0, 0), (False, 1, 3, 2))
     for timing, kernel, block, wpc in shapes:
         s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
         s.set_launch(kernel, block, wpc)
@@ -195,15 +205,29 @@ def test_graph_replay_equals_eager_and_block_shapes_agree():
             assert n == 5 * 23 and ms > 0
     for o in outs[1:]:
         assert np.array_equal(outs[0], o)
-    # a kernel variant this build does not provide is refused
-    for bad in ((1, 0, 0), (0, 5, 0), (0, 7, 65)):
+    # the matrix-core variant: bitwise stable over its own shapes and
+    # graph/eager, equal to variant 0 to rounding
+    mouts = []
+    for timing, kernel, block, wpc in mma_shapes:
+        s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
+        s.set_launch(kernel, block, wpc)
+        s.enable_timing(timing)
+        s.set_source(0, w["source"], w["f0"], w["t0"], w["amp"])
+        s.set_fields(0, q0)
+        s.step(23)
+        mouts.append(s.get_fields(0))
+    for o in mouts[1:]:
+        assert np.array_equal(mouts[0], o)
+    assert rel_l2(mouts[0], outs[0]) <= FP64_TOL
+    # a kernel variant or shape this build does not provide is refused
+    for bad in ((2, 0, 0), (0, 5, 0), (1, 5, 0), (0, 7, 65)):
         with pytest.raises(DGWError) as ei:
             s.set_launch(*bad)
         assert ei.value.status == "DGW_EINVAL"
 
 
-@pytest.mark.parametrize("precision", [64, 32])
-def test_batched_shots_match_single_shot_runs(precision):
+@pytest.mark.parametrize("precision,kernel", [(p, kv) for kv in KERNELS for p in (64, 32)])
+def test_batched_shots_match_single_shot_runs(precision, kernel):
     mesh = W.kuhn_cube(3, 1.0)
     K = mesh["etov"].shape[0]
     rho, lam, mu = _random_medium(K, 3)
@@ -213,17 +237,17 @@ def test_batched_shots_match_single_shot_runs(precision):
     srcs = np.array([[0.2, 0.3, 0.4], [0.7, 0.6, 0.5], [0.5, 0.5, 0.9]])
     lens = [7, 12, 3]
     rec = np.array([[0.4, 0.4, 1.0], [0.6, 0.2, 1.0]])
-    say("case batched shots precision=%d" % precision)
+    say("case batched shots precision=%d kernel=%d" % (precision, kernel))
     b = gpu_solver(mesh, N, rho, lam, mu, dt, precision, nshots=3)
     # persistent grid looping over (shot, block) items
-    b.set_launch(0, 0, 2)
+    b.set_launch(kernel, 0, 2)
     for i in range(3):
         b.set_source(i, srcs[i], 6.0, 0.1, 1.0, nsteps=lens[i])
         b.set_receivers(i, rec, 20)
     b.step(15)
     for i in range(3):
         assert b.shot_steps(i) == lens[i]
-        one = gpu_solver(mesh, N, rho, lam, mu, dt, precision)
+        one = gpu_solver(mesh, N, rho, lam, mu, dt, precision, kernel=kernel)
         one.set_source(0, srcs[i], 6.0, 0.1, 1.0, nsteps=lens[i])
         one.set_receivers(0, rec, 20)
         one.step(15)
