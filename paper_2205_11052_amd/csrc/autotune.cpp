@@ -77,7 +77,7 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *kernel,
   std::vector<Shape> opts;
   for (int kv : {0, 1})
     for (int be : stage_block_choices(kv, c->R.N, c->precision))
-      for (int w : {0, 2, 4, 8, 16}) opts.push_back({kv, be, w});
+      for (int w : {0, 1, 2, 3, 4, 8, 16}) opts.push_back({kv, be, w});
   auto report = [&](const Shape &o) {
     if (kernel) *kernel = o.kernel;
     if (elems_per_block) *elems_per_block = o.be;

@@ -103,7 +103,7 @@ template <int N, typename real, int BE>
 __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real *sq,
                                             real *sfl, const double *smeta, int nE,
                                             int64_t k0, int shot, int64_t step,
-                                            real *qout, real *res) {
+                                            real *qout, real *res, int oz, int tid) {
   using M = Mma<real>;
   using v4 = typename M::v4;
   constexpr int Np = Sz<N>::Np, NF = 4 * Sz<N>::Nfp;
@@ -113,7 +113,7 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
   constexpr int NT = (9 * BE + 15) / 16;    // column tiles
   constexpr int UP = (BE * 9 * Np + kThreads - 1) / kThreads;  // update items
   static_assert(9 * Np <= 9 * NF, "the flux buffer holds the right-hand side");
-  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4;
+  const int lane = tid & 63, g = lane >> 4;
   const int span = nE * 9 * Np;
   const bool first = A.rk_a == 0.0;
   // residual loads of this thread's update items, issued first
@@ -170,7 +170,7 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const real ca0 = c[a][0], ca1 = c[a][1], ca2 = c[a][2];
-      const real *Ab = A.Avol + (size_t)a * KS * MT * 64 + lane;
+      const real *Ab = A.Avol + (size_t)a * KS * MT * 64 + lane + oz;
       for (int ks = 0; ks < KS; ++ks) {
         const int j = 4 * ks + g;
         real b = 0;
@@ -181,7 +181,7 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
     }
     // lift: the column's flux on the 4 Nfp face nodes
     const real *fl = sfl + (e * 9 + k) * NF;
-    const real *Al = A.Alift + lane;
+    const real *Al = A.Alift + lane + oz;
     for (int ks = 0; ks < KL; ++ks) {
       const real b = fl[4 * ks + g];
 #pragma unroll
@@ -229,10 +229,9 @@ template <int N, typename real, int BE>
 __device__ __forceinline__ void phase3_nodes(const StageArgs<real> &A, const real *sq,
                                              const real *sfl, const double *smeta,
                                              int nE, int64_t k0, int shot, int64_t step,
-                                             real *qout, real *res) {
+                                             real *qout, real *res, int oz, int tid) {
   constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Sz<N>::Nfp;
   constexpr int UJ = Np % 7 == 0 ? 7 : Np % 5 == 0 ? 5 : 4;  // divides Np
-  const int tid = threadIdx.x;
   for (int t = tid; t < nE * Np; t += kThreads) {
     const int e = t / Np, i = t - e * Np;
     const real *qe = sq + e * 9 * Np;
@@ -242,7 +241,7 @@ __device__ __forceinline__ void phase3_nodes(const StageArgs<real> &A, const rea
     for (int c = 0; c < 9; ++c) dr[c] = ds[c] = dt[c] = (real)0;
     // column i of the transposed operators, walked in chunks of UJ rows:
     // inside a chunk every offset is an immediate
-    const real *pr = A.DrT + i, *ps = A.DsT + i, *pt = A.DtT + i;
+    const real *pr = A.DrT + i + oz, *ps = A.DsT + i + oz, *pt = A.DtT + i + oz;
 #pragma unroll 1   // a short chunk loop unrolled would hoist every load
     for (int j0 = 0; j0 < Np; j0 += UJ) {
 #pragma unroll
@@ -289,7 +288,7 @@ __device__ __forceinline__ void phase3_nodes(const StageArgs<real> &A, const rea
     // lift: velocity flux over all faces; lifted dv per face, then the
     // stress components from it and the face normal
     const real *fle = sfl + e * NF * 6;
-    const real *pl = A.LIFTT + i;
+    const real *pl = A.LIFTT + i + oz;
     real V0 = 0, V1 = 0, V2 = 0;
 #pragma unroll 1   // unrolled, the persistent form hoists too much and spills
     for (int f = 0; f < 4; ++f) {
@@ -337,9 +336,43 @@ __device__ __forceinline__ void phase3_nodes(const StageArgs<real> &A, const rea
   }
 }
 
+// Face tables of a block for this thread's face items: the packed
+// connectivity code and, for interior faces, the neighbour trace's offset
+// in the shot's field array.  Loaded ahead of the block (by the persistent
+// form one block early) so the neighbour gathers issue with the block's own
+// loads.
+template <int N, int BE>
+struct FaceTab {
+  static constexpr int FI = (BE * 4 * Sz<N>::Nfp + kThreads - 1) / kThreads;
+  int cn[FI];
+  int64_t gb[FI];
+};
+
+template <int N, typename real, int BE>
+__device__ __forceinline__ void face_tables(const StageArgs<real> &A, int64_t item,
+                                            int64_t nblk, FaceTab<N, BE> &T) {
+  constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Nfp;
+  const int shot = (int)(item / nblk);
+  const int64_t k0 = (item - (int64_t)shot * nblk) * BE;
+  const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
+#pragma unroll
+  for (int u = 0; u < FaceTab<N, BE>::FI; ++u) {
+    const int t = threadIdx.x + u * kThreads;
+    T.cn[u] = CONN_ABSORB;
+    T.gb[u] = 0;
+    if (k0 < A.K && t < nE * NF) {
+      const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
+      const int64_t k = k0 + e;
+      const int cn = A.conn[k * 4 + f];
+      T.cn[u] = cn;
+      if (cn >= 0) T.gb[u] = (int64_t)(cn >> 5) * 9 * Np + A.nbnode[k * NF + fm];
+    }
+  }
+}
+
 template <int N, typename real, int BE, int V>
 __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t item,
-                                           int64_t nblk) {
+                                           int64_t nblk, const FaceTab<N, BE> &T) {
   constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Sz<N>::Nfp;
   constexpr int FI = (BE * NF + kThreads - 1) / kThreads;   // face items per thread
   // declared here (not passed in) so every access stays an LDS access
@@ -358,6 +391,11 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
   real *__restrict__ qout = A.q_out + shot * A.shot_stride;
   real *__restrict__ res = A.res + shot * A.shot_stride;
   const int tid = threadIdx.x;
+  // an opaque zero added to the operator addresses: in the persistent form
+  // the compiler would otherwise hoist every operator load (they depend on
+  // the thread only) out of the item loop, far beyond the register file
+  int oz;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(oz));
 
   // ---- 1. all global reads of the item's fields are issued together ----
   for (int t = tid; t < nE * 9 * Np; t += kThreads) sq[t] = qin[k0 * 9 * Np + t];
@@ -368,18 +406,10 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
   int cnv[FI];
 #pragma unroll
   for (int u = 0; u < FI; ++u) {
-    const int t = tid + u * kThreads;
-    cnv[u] = CONN_ABSORB;
-    if (t < nE * NF) {
-      const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
-      const int64_t k = k0 + e;
-      const int cn = A.conn[k * 4 + f];
-      cnv[u] = cn;
-      if (cn >= 0) {
-        const int64_t base = (int64_t)(cn >> 5) * 9 * Np + A.nbnode[k * NF + fm];
+    cnv[u] = T.cn[u];
+    if (cnv[u] >= 0) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) qp[u][c] = qin[base + c * Np];
-      }
+      for (int c = 0; c < 9; ++c) qp[u][c] = qin[T.gb[u] + c * Np];
     }
   }
   __syncthreads();
@@ -462,25 +492,37 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
 
 
   if constexpr (V == 1)
-    phase3_mfma<N, real, BE>(A, sq, sfl, smeta, nE, k0, shot, step, qout, res);
+    phase3_mfma<N, real, BE>(A, sq, sfl, smeta, nE, k0, shot, step, qout, res, oz, tid);
   else
-    phase3_nodes<N, real, BE>(A, sq, sfl, smeta, nE, k0, shot, step, qout, res);
+    phase3_nodes<N, real, BE>(A, sq, sfl, smeta, nE, k0, shot, step, qout, res, oz, tid);
 }
 
 // One work-group per item.
 template <int N, typename real, int BE, int V>
 __global__ void __launch_bounds__(kThreads)
 stage_kernel(StageArgs<real> A, int64_t nblk, int64_t total) {
-  stage_item<N, real, BE, V>(A, xcd_item(blockIdx.x, total), nblk);
+  const int64_t item = xcd_item(blockIdx.x, total);
+  FaceTab<N, BE> T;
+  face_tables<N, real, BE>(A, item, nblk, T);
+  stage_item<N, real, BE, V>(A, item, nblk, T);
 }
 
-// Persistent grid (a multiple of 8 work-groups) looping over the items.
+// Persistent grid (a multiple of 8 work-groups) looping over the items;
+// the next item's face tables are loaded while the current one is processed.
 template <int N, typename real, int BE, int V>
 __global__ void __launch_bounds__(kThreads)
 stage_kernel_persistent(StageArgs<real> A, int64_t nblk, int64_t total) {
-  for (int64_t L = blockIdx.x; L < total; L += gridDim.x) {
-    stage_item<N, real, BE, V>(A, xcd_item(L, total), nblk);
+  int64_t L = blockIdx.x;
+  FaceTab<N, BE> T;
+  if (L < total) face_tables<N, real, BE>(A, xcd_item(L, total), nblk, T);
+  for (; L < total; L += gridDim.x) {
+    const int64_t item = xcd_item(L, total);
+    FaceTab<N, BE> Tn;
+    if (L + gridDim.x < total)
+      face_tables<N, real, BE>(A, xcd_item(L + gridDim.x, total), nblk, Tn);
+    stage_item<N, real, BE, V>(A, item, nblk, T);
     __syncthreads();   // LDS is reused by the next item
+    T = Tn;
   }
 }
 
