@@ -53,9 +53,9 @@ META_BYTES = 48 * 8 + 4 * 4        # per-element data + packed connectivity
 # is reported only while the kernel source hashes to the value it was
 # measured for and the same launch shape runs; otherwise traffic is null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "c96121f70c8c80b40bb678046f3b5d8506c3a700981965ce8f20c6a48e18ad8f",
+    "kernel_source_sha256": "b423f9c104b3a10cf673ace71c572f0e668a70233f25b1ad0e7cc0ebe55a7ecf",
     "launch_shape": (1, 7, 0),
-    "bytes_per_launch": 967740676,
+    "bytes_per_launch": 968190278,
 }
 
 
