@@ -168,3 +168,48 @@ def test_gradient_matches_central_differences():
     s.set_material(*base)
     say("FD worst relative error %.2e over %d elements" % (worst, len(elems)))
     assert worst <= 1e-4
+
+
+def test_full_size_gradient_matches_central_differences():
+    """The gradient workload at full size (6*16^3 = 24576 elements, order 3,
+    blob-perturbed starting medium), 300 steps with checkpoints every 100,
+    observed data zero (the misfit is then 1/2 dt sum trace^2, so no input
+    comes from the GPU path): GPU FP64 adjoint vs central differences of the
+    GPU forward on 3 seeded elements, relative error <= 1e-4."""
+    nsteps = 300
+    ws = W.build_workload("c3_adjoint", medium="blob")
+    wt = W.build_workload("c3_adjoint")
+    say("case full-size FD check K=%d steps=%d" % (ws["K"], nsteps))
+    s = gpu_solver(ws["mesh"], ws["N"], wt["rho"], wt["lam"], wt["mu"], 1.0)
+    dt = s.suggest_dt(wt["cfl"])                # fixed from the true medium
+    s.set_dt(dt)
+    s.set_material(ws["rho"], ws["lam"], ws["mu"])
+    s.set_source(0, ws["source"], ws["f0"], ws["t0"], ws["amp"])
+    s.set_receivers(0, ws["receivers"], nsteps)
+    d = np.zeros((1, len(ws["receivers"]), 3, nsteps))
+    s.zero_fields()
+    s.forward_checkpointed(nsteps, 100, d)
+    g = [x[0] for x in s.adjoint()]
+    gmax = max(np.abs(x).max() for x in g)
+    assert gmax > 0
+    eligible = np.nonzero(np.maximum.reduce([np.abs(x) for x in g]) >= 1e-3 * gmax)[0]
+    elems = np.random.default_rng(52).choice(eligible, size=3, replace=False)
+    base = [np.array(ws["rho"]), np.array(ws["lam"]), np.array(ws["mu"])]
+    worst, n = 0.0, 0
+    for k in elems:
+        for p in range(3):
+            if abs(g[p][k]) < 1e-3 * gmax:
+                continue
+            delta = 1e-6 * base[p][k]
+            vals = []
+            for sgn in (1, -1):
+                m = [b.copy() for b in base]
+                m[p][k] += sgn * delta
+                s.set_material(*m)
+                s.zero_fields()
+                vals.append(s.forward_checkpointed(nsteps, nsteps, d)[0])
+            fd = (vals[0] - vals[1]) / (2 * delta)
+            worst = max(worst, abs(fd - g[p][k]) / abs(fd))
+            n += 1
+    say("full-size FD worst relative error %.2e over %d entries" % (worst, n))
+    assert n > 0 and worst <= 1e-4

@@ -5,6 +5,8 @@ FP64 relative L2 <= 1e-12, FP32 relative L2 <= 1e-5 against the FP64 oracle
 on the same seeded inputs.
 """
 
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -112,13 +114,12 @@ def test_reduced_layered_source_receivers_fp64():
     assert err <= FP64_TOL and terr <= FP64_TOL
 
 
-def test_full_size_layered_fp64_bench_launch():
-    """Full 82944-element mesh at order 4 in every launch shape the
-    benchmark's autotuner can pick: random fields everywhere (every face
-    type and element exercised), the source and receivers active, two steps
-    against the oracle."""
+@functools.lru_cache(maxsize=1)
+def _full_c1_oracle():
+    """The full 82944-element order-4 mesh with random fields everywhere
+    (every face type and element exercised), source and receivers active:
+    two oracle steps, shared by the full-size tests."""
     w = W.build_workload("c1_layered_n24")
-    say("case full c1 fp64 K=%d" % w["K"])
     P = oracle_problem(w["mesh"], w["N"])
     dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
     P.set_source(w["source"], w["f0"], 0.05, w["amp"])
@@ -126,8 +127,16 @@ def test_full_size_layered_fp64_bench_launch():
     q0 = random_fields(w["K"], P.Np, 7)
     q_ora, tr_ora = oracle_run(P, q0, w["rho"], w["lam"], w["mu"], dt, 2,
                                record=True)
+    return w, dt, q0, q_ora, tr_ora
+
+
+def test_full_size_layered_fp64_bench_launch():
+    """Full 82944-element mesh at order 4 in every launch shape the
+    benchmark's autotuner can pick, two steps against the oracle."""
+    w, dt, q0, q_ora, tr_ora = _full_c1_oracle()
+    say("case full c1 fp64 K=%d" % w["K"])
     shapes = [(kv, be, wpc) for kv in KERNELS for be in (7, 3)
-              for wpc in (0, 2, 4, 8, 16)]
+              for wpc in (0, 1, 2, 3, 4, 8, 16)]
     s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
     s.set_source(0, w["source"], w["f0"], 0.05, w["amp"])
     s.set_receivers(0, w["receivers"], 8)
@@ -139,6 +148,98 @@ def test_full_size_layered_fp64_bench_launch():
         terr = rel_l2(s.read_traces(0), tr_ora)
         say("full c1 shape %s fields %.3e traces %.3e" % (shape, err, terr))
         assert err <= FP64_TOL and terr <= FP64_TOL
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_full_size_layered_fp32_bench_launch(kernel):
+    """The FP32 form on the full 82944-element order-4 mesh in the shapes
+    the benchmark times, against the FP64 oracle."""
+    w, dt, q0, q_ora, tr_ora = _full_c1_oracle()
+    say("case full c1 fp32 kernel=%d" % kernel)
+    s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt, 32)
+    s.set_source(0, w["source"], w["f0"], 0.05, w["amp"])
+    s.set_receivers(0, w["receivers"], 8)
+    for be in (7, 3):
+        s.set_launch(kernel, be, 0)
+        s.set_fields(0, q0)
+        s.step(2)
+        err = rel_l2(s.get_fields(0), q_ora)
+        terr = rel_l2(s.read_traces(0), tr_ora)
+        say("full c1 fp32 kernel %d be %d fields %.3e traces %.3e" % (kernel, be, err, terr))
+        assert err <= FP32_TOL and terr <= FP32_TOL
+
+
+def test_full_size_order6_variants_agree_and_dissipate():
+    """Order 6 (84 nodes) on the full 82944-element mesh, where the oracle
+    is too slow for a full run: the two kernel variants agree to the FP64
+    bar, the discrete energy does not grow over the steps (no source; the
+    upwind flux and the absorbing and free-surface boundaries only
+    dissipate; checked in FP64), and FP32 agrees with FP64 to the FP32
+    bar.  Oracle parity
+    at order 6 is covered on smaller meshes."""
+    w = W.build_workload("c1_layered_n24", N=6)
+    say("case full order 6 K=%d" % w["K"])
+    q0 = random_fields(w["K"], 84, 17)
+    dt = None
+    outs = {}
+    for prec, kernel in ((64, 0), (64, 1), (32, 1)):
+        from paper_2205_11052_amd import Solver
+        s = Solver(6, prec, 1)
+        s.set_mesh_dict(w["mesh"])
+        s.set_material(w["rho"], w["lam"], w["mu"])
+        if dt is None:
+            dt = s.suggest_dt(w["cfl"])
+        s.set_dt(dt)
+        s.set_launch(kernel)
+        s.set_fields(0, q0)
+        e = [s.energy(0)]
+        for _ in range(3):
+            s.step(1)
+            e.append(s.energy(0))
+        outs[(prec, kernel)] = s.get_fields(0)
+        say("order 6 fp%d kernel %d energies %s" % (prec, kernel, e))
+        if prec == 64:
+            for a, b in zip(e[:-1], e[1:]):
+                assert b <= a * (1 + 1e-10)
+        s.close()
+    assert rel_l2(outs[(64, 1)], outs[(64, 0)]) <= FP64_TOL
+    assert rel_l2(outs[(32, 1)], outs[(64, 0)]) <= FP32_TOL
+
+
+def test_full_size_batched_32_shots():
+    """The benchmark's batched form at full size: 32 FP32 shots of uneven
+    length on the 82944-element mesh, one launch per stage over all shots;
+    the first and last shots equal single-shot runs bitwise."""
+    w = W.build_workload("c1_layered_n24")
+    pos, lens = W.batched_shots()
+    lens = np.minimum(lens, 4)
+    lens[0] = 2                         # one shot stops early
+    say("case full batched 32 shots")
+    from paper_2205_11052_amd import Solver
+    b = Solver(4, 32, len(pos))
+    b.set_mesh_dict(w["mesh"])
+    b.set_material(w["rho"], w["lam"], w["mu"])
+    dt = b.suggest_dt(w["cfl"])
+    b.set_dt(dt)
+    for i in range(len(pos)):
+        b.set_source(i, pos[i], w["f0"], w["t0"], w["amp"], nsteps=int(lens[i]))
+        b.set_receivers(i, w["receivers"], 8)
+    b.set_launch(1, 7, 0)
+    b.step(4)
+    for i in (0, len(pos) - 1):
+        assert b.shot_steps(i) == lens[i]
+        one = Solver(4, 32, 1)
+        one.set_mesh_dict(w["mesh"])
+        one.set_material(w["rho"], w["lam"], w["mu"])
+        one.set_dt(dt)
+        one.set_source(0, pos[i], w["f0"], w["t0"], w["amp"], nsteps=int(lens[i]))
+        one.set_receivers(0, w["receivers"], 8)
+        one.set_launch(1, 7, 0)
+        one.step(4)
+        assert np.array_equal(b.get_fields(i), one.get_fields(0))
+        assert np.array_equal(b.read_traces(i), one.read_traces(0))
+        one.close()
+    b.close()
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
