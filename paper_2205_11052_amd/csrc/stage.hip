@@ -61,6 +61,28 @@ __device__ inline int64_t xcd_item(int64_t L, int64_t total) {
   return start + (L >> 3);
 }
 
+// A contiguous span of `cnt` values at element offset `off` of a
+// 16-byte-aligned array, split for 16-byte vector access: `hd` scalars up
+// to the first aligned address, `nv` vectors of VW values, `tl` scalars.
+template <typename real>
+struct real2v {
+  real r, q;
+};
+
+template <typename real>
+struct Span16 {
+  static constexpr int VW = 16 / (int)sizeof(real);
+  typedef real vec __attribute__((ext_vector_type(VW)));
+  int hd, nv, tl;
+  __device__ Span16(int64_t off, int cnt) {
+    const int mis = (int)(off % VW);
+    hd = (VW - mis) % VW;
+    if (hd > cnt) hd = cnt;
+    nv = (cnt - hd) / VW;
+    tl = cnt - hd - nv * VW;
+  }
+};
+
 // Matrix-core (MFMA) 16x16x4 tiles.  Lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16] of the 16x4 and 4x16 operands (both precisions); the
 // 16x16 accumulator lives in four registers per lane, lane l holding column
@@ -111,18 +133,26 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
   constexpr int KS = (Np + 3) / 4;          // k-steps per reference direction
   constexpr int KL = NF / 4;                // k-steps of the lift (4 Nfp % 4 == 0)
   constexpr int NT = (9 * BE + 15) / 16;    // column tiles
-  constexpr int UP = (BE * 9 * Np + kThreads - 1) / kThreads;  // update items
   static_assert(9 * Np <= 9 * NF, "the flux buffer holds the right-hand side");
   const int lane = tid & 63, g = lane >> 4;
   const int span = nE * 9 * Np;
   const bool first = A.rk_a == 0.0;
-  // residual loads of this thread's update items, issued first
-  real rold[UP];
+  // residual loads of this thread's update items (16-byte vectors over the
+  // block's contiguous span), issued first
+  using SP = Span16<real>;
+  constexpr int UV = (BE * 9 * Np / SP::VW + kThreads - 1) / kThreads;
+  const SP sp(shot * A.shot_stride + k0 * 9 * Np, span);
+  real *rs = res + k0 * 9 * Np, *qo = qout + k0 * 9 * Np;
+  typename SP::vec rv[UV];
 #pragma unroll
-  for (int u = 0; u < UP; ++u) {
-    const int t = tid + u * kThreads;
-    rold[u] = (!first && t < span) ? res[k0 * 9 * Np + t] : (real)0;
+  for (int u = 0; u < UV; ++u) {
+    const int j = tid + u * kThreads;
+    if (!first && j < sp.nv) rv[u] = ((const typename SP::vec *)(rs + sp.hd))[j];
+    else rv[u] = typename SP::vec{};
   }
+  const int tl0 = sp.hd + SP::VW * sp.nv;
+  const real rh = (!first && tid < sp.hd) ? rs[tid] : (real)0;
+  const real rt = (!first && tid < sp.tl) ? rs[tl0 + tid] : (real)0;
   v4 acc[NT > 4 ? 2 : 1][MT];
   int ntl = 0;
   for (int nt = tid >> 6; nt < NT; nt += kThreads / 64, ++ntl) {
@@ -208,19 +238,39 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
   const real ra = (real)A.rk_a, rb = (real)A.rk_b, rdt = (real)A.dt;
   const int64_t es = (int64_t)A.src_elem[shot] - k0;   // source element in block
   double s = 0.0;
-  const double *sp = A.src_par + 10 * shot;
-  if (es >= 0 && es < nE) s = ricker_d(((double)step + A.rk_c) * A.dt, sp[6], sp[7], sp[8]);
-  real *qo = qout + k0 * 9 * Np, *rs = res + k0 * 9 * Np;
-#pragma unroll
-  for (int u = 0; u < UP; ++u) {
-    const int t = tid + u * kThreads;
-    if (t >= span) continue;
+  const double *spar = A.src_par + 10 * shot;
+  if (es >= 0 && es < nE) s = ricker_d(((double)step + A.rk_c) * A.dt, spar[6], spar[7], spar[8]);
+  auto update = [&](int t, real rold) -> real2v<real> {
     real rhs = sfl[t];
     const int e = t / (9 * Np), ci = t - e * 9 * Np, c = ci / Np, i = ci - c * Np;
-    if (e == es && c >= 3) rhs += (real)(s * sp[c - 3] * A.src_vec[shot * Np + i]);
-    const real rn = first ? rdt * rhs : ra * rold[u] + rdt * rhs;
-    rs[t] = rn;
-    qo[t] = sq[t] + rb * rn;
+    if (e == es && c >= 3) rhs += (real)(s * spar[c - 3] * A.src_vec[shot * Np + i]);
+    const real rn = first ? rdt * rhs : ra * rold + rdt * rhs;
+    return {rn, sq[t] + rb * rn};
+  };
+#pragma unroll
+  for (int u = 0; u < UV; ++u) {
+    const int j = tid + u * kThreads;
+    if (j >= sp.nv) continue;
+    const int b = sp.hd + SP::VW * j;
+    typename SP::vec nr, nq;
+#pragma unroll
+    for (int l = 0; l < SP::VW; ++l) {
+      const real2v<real> o = update(b + l, rv[u][l]);
+      nr[l] = o.r;
+      nq[l] = o.q;
+    }
+    *(typename SP::vec *)(rs + b) = nr;
+    *(typename SP::vec *)(qo + b) = nq;
+  }
+  if (tid < sp.hd) {
+    const real2v<real> o = update(tid, rh);
+    rs[tid] = o.r;
+    qo[tid] = o.q;
+  }
+  if (tid < sp.tl) {
+    const real2v<real> o = update(tl0 + tid, rt);
+    rs[tl0 + tid] = o.r;
+    qo[tl0 + tid] = o.q;
   }
 }
 
@@ -398,9 +448,28 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
   asm volatile("v_mov_b32 %0, 0" : "=v"(oz));
 
   // ---- 1. all global reads of the item's fields are issued together ----
-  for (int t = tid; t < nE * 9 * Np; t += kThreads) sq[t] = qin[k0 * 9 * Np + t];
-  for (int t = tid; t < nE * DGW_META; t += kThreads)
-    smeta[t] = A.meta[k0 * DGW_META + t];
+  {
+    // fields (16-byte loads; the span starts wherever the block starts)
+    using SP = Span16<real>;
+    const int64_t off = shot * A.shot_stride + k0 * 9 * Np;
+    const SP sp(off, nE * 9 * Np);
+    const real *src = qin + k0 * 9 * Np;
+    if (tid < sp.hd) sq[tid] = src[tid];
+    const typename SP::vec *sv = (const typename SP::vec *)(src + sp.hd);
+    for (int t = tid; t < sp.nv; t += kThreads) {
+      const typename SP::vec v = sv[t];
+#pragma unroll
+      for (int l = 0; l < SP::VW; ++l) sq[sp.hd + SP::VW * t + l] = v[l];
+    }
+    if (tid < sp.tl) sq[sp.hd + SP::VW * sp.nv + tid] = src[sp.hd + SP::VW * sp.nv + tid];
+    // per-element data (48 doubles per element: 16-byte aligned)
+    const double2 *mv = (const double2 *)(A.meta + k0 * DGW_META);
+    for (int t = tid; t < nE * DGW_META / 2; t += kThreads) {
+      const double2 v = mv[t];
+      smeta[2 * t] = v.x;
+      smeta[2 * t + 1] = v.y;
+    }
+  }
   // neighbour traces of this thread's face nodes go to registers
   real qp[FI][9];
   int cnv[FI];
