@@ -117,8 +117,23 @@ __global__ void __launch_bounds__(kT) adj_lift_kernel(AdjArgs<real> A) {
   const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
   const int64_t off = shot * A.shot_stride + k0 * 9 * Np;
   const real b = (real)A.rk_b;
-  for (int t = threadIdx.x; t < nE * 9 * Np; t += kT)
-    sw[t] = A.lam_r[off + t] + b * A.lam_q[off + t];
+  {
+    // w = lam_r + b lam_q over the block's contiguous span (16-byte loads)
+    using SP = Span16<real>;
+    const SP sp(off, nE * 9 * Np);
+    const real *lr = A.lam_r + off, *lq = A.lam_q + off;
+    const int tid = threadIdx.x;
+    if (tid < sp.hd) sw[tid] = lr[tid] + b * lq[tid];
+    for (int t = tid; t < sp.nv; t += kT) {
+      const int o = sp.hd + SP::VW * t;
+      const typename SP::vec x = *(const typename SP::vec *)(lr + o),
+                             y = *(const typename SP::vec *)(lq + o);
+#pragma unroll
+      for (int l = 0; l < SP::VW; ++l) sw[o + l] = x[l] + b * y[l];
+    }
+    const int o = sp.hd + SP::VW * sp.nv;
+    if (tid < sp.tl) sw[o + tid] = lr[o + tid] + b * lq[o + tid];
+  }
   for (int t = threadIdx.x; t < nE * 4; t += kT)
     sfs[t] = A.meta[(k0 + t / 4) * DGW_META + M_FSCALE + (t & 3)];
   __syncthreads();
@@ -165,10 +180,32 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
   const real b = (real)A.rk_b;
   const int tid = threadIdx.x;
 
-  for (int t = tid; t < nE * 9 * Np; t += kT) {
-    const int64_t g = k0 * 9 * Np + t;
-    sw[t] = lr[g] + b * lq[g];
-    sq[t] = q[g];
+  {
+    // w = lam_r + b lam_q and the stage input q over the block's contiguous
+    // span (16-byte loads)
+    using SP = Span16<real>;
+    const SP sp(soff + k0 * 9 * Np, nE * 9 * Np);
+    const real *lrb = lr + k0 * 9 * Np, *lqb = lq + k0 * 9 * Np, *qb = q + k0 * 9 * Np;
+    if (tid < sp.hd) {
+      sw[tid] = lrb[tid] + b * lqb[tid];
+      sq[tid] = qb[tid];
+    }
+    for (int t = tid; t < sp.nv; t += kT) {
+      const int o = sp.hd + SP::VW * t;
+      const typename SP::vec x = *(const typename SP::vec *)(lrb + o),
+                             y = *(const typename SP::vec *)(lqb + o),
+                             z = *(const typename SP::vec *)(qb + o);
+#pragma unroll
+      for (int l = 0; l < SP::VW; ++l) {
+        sw[o + l] = x[l] + b * y[l];
+        sq[o + l] = z[l];
+      }
+    }
+    const int o = sp.hd + SP::VW * sp.nv;
+    if (tid < sp.tl) {
+      sw[o + tid] = lrb[o + tid] + b * lqb[o + tid];
+      sq[o + tid] = qb[o + tid];
+    }
   }
   for (int t = tid; t < nE * DGW_META; t += kT) smeta[t] = A.meta[k0 * DGW_META + t];
   for (int t = tid; t < nE * 4; t += kT) scn[t] = A.conn[k0 * 4 + t];

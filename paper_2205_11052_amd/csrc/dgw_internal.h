@@ -90,6 +90,23 @@ struct StageArgs {
   double rk_a, rk_b, rk_c, dt;
 };
 
+// A contiguous span of `cnt` values at element offset `off` of a
+// 16-byte-aligned array, split for 16-byte vector access: `hd` scalars up
+// to the first aligned address, `nv` vectors of VW values, `tl` scalars.
+template <typename real>
+struct Span16 {
+  static constexpr int VW = 16 / (int)sizeof(real);
+  typedef real vec __attribute__((ext_vector_type(VW)));
+  int hd, nv, tl;
+  __device__ Span16(int64_t off, int cnt) {
+    const int mis = (int)(off % VW);
+    hd = (VW - mis) % VW;
+    if (hd > cnt) hd = cnt;
+    nv = (cnt - hd) / VW;
+    tl = cnt - hd - nv * VW;
+  }
+};
+
 struct RecArgs {
   const void *q;                // current state (real)
   int64_t shot_stride;

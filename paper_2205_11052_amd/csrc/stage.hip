@@ -61,26 +61,9 @@ __device__ inline int64_t xcd_item(int64_t L, int64_t total) {
   return start + (L >> 3);
 }
 
-// A contiguous span of `cnt` values at element offset `off` of a
-// 16-byte-aligned array, split for 16-byte vector access: `hd` scalars up
-// to the first aligned address, `nv` vectors of VW values, `tl` scalars.
 template <typename real>
 struct real2v {
   real r, q;
-};
-
-template <typename real>
-struct Span16 {
-  static constexpr int VW = 16 / (int)sizeof(real);
-  typedef real vec __attribute__((ext_vector_type(VW)));
-  int hd, nv, tl;
-  __device__ Span16(int64_t off, int cnt) {
-    const int mis = (int)(off % VW);
-    hd = (VW - mis) % VW;
-    if (hd > cnt) hd = cnt;
-    nv = (cnt - hd) / VW;
-    tl = cnt - hd - nv * VW;
-  }
 };
 
 // Matrix-core (MFMA) 16x16x4 tiles.  Lane l holds A[l % 16][l / 16] and
