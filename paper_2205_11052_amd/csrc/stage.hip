@@ -126,16 +126,6 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
   constexpr int UV = (BE * 9 * Np / SP::VW + kThreads - 1) / kThreads;
   const SP sp(shot * A.shot_stride + k0 * 9 * Np, span);
   real *rs = res + k0 * 9 * Np, *qo = qout + k0 * 9 * Np;
-  typename SP::vec rv[UV];
-#pragma unroll
-  for (int u = 0; u < UV; ++u) {
-    const int j = tid + u * kThreads;
-    if (!first && j < sp.nv) rv[u] = ((const typename SP::vec *)(rs + sp.hd))[j];
-    else rv[u] = typename SP::vec{};
-  }
-  const int tl0 = sp.hd + SP::VW * sp.nv;
-  const real rh = (!first && tid < sp.hd) ? rs[tid] : (real)0;
-  const real rt = (!first && tid < sp.tl) ? rs[tl0 + tid] : (real)0;
   v4 acc[NT > 4 ? 2 : 1][MT];
   int ntl = 0;
   for (int nt = tid >> 6; nt < NT; nt += kThreads / 64, ++ntl) {
@@ -201,6 +191,16 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
       for (int mt = 0; mt < MT; ++mt) ac[mt] = M::mma(Al[(ks * MT + mt) * 64], b, ac[mt]);
     }
   }
+  typename SP::vec rv[UV];
+#pragma unroll
+  for (int u = 0; u < UV; ++u) {
+    const int j = tid + u * kThreads;
+    if (!first && j < sp.nv) rv[u] = ((const typename SP::vec *)(rs + sp.hd))[j];
+    else rv[u] = typename SP::vec{};
+  }
+  const int tl0 = sp.hd + SP::VW * sp.nv;
+  const real rh = (!first && tid < sp.hd) ? rs[tid] : (real)0;
+  const real rt = (!first && tid < sp.tl) ? rs[tl0 + tid] : (real)0;
   __syncthreads();   // every wave is done with the flux buffer
   // right-hand side to LDS in the block's (element, field, node) order
   ntl = 0;
@@ -371,9 +371,9 @@ __device__ __forceinline__ void phase3_nodes(const StageArgs<real> &A, const rea
 
 // Face tables of a block for this thread's face items: the packed
 // connectivity code and, for interior faces, the neighbour trace's offset
-// in the shot's field array.  Loaded ahead of the block (by the persistent
-// form one block early) so the neighbour gathers issue with the block's own
-// loads.
+// in the shot's field array.  Loaded ahead of the gathers (by the persistent
+// form one block early).  Both tables are read unconditionally (the index is
+// clamped into the block) so every table load is in flight at once.
 template <int N, int BE>
 struct FaceTab {
   static constexpr int FI = (BE * 4 * Sz<N>::Nfp + kThreads - 1) / kThreads;
@@ -391,21 +391,72 @@ __device__ __forceinline__ void face_tables(const StageArgs<real> &A, int64_t it
 #pragma unroll
   for (int u = 0; u < FaceTab<N, BE>::FI; ++u) {
     const int t = threadIdx.x + u * kThreads;
-    T.cn[u] = CONN_ABSORB;
-    T.gb[u] = 0;
-    if (k0 < A.K && t < nE * NF) {
-      const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
-      const int64_t k = k0 + e;
-      const int cn = A.conn[k * 4 + f];
-      T.cn[u] = cn;
-      if (cn >= 0) T.gb[u] = (int64_t)(cn >> 5) * 9 * Np + A.nbnode[k * NF + fm];
-    }
+    const bool ok = k0 < A.K && t < nE * NF;
+    const int tt = ok ? t : 0;
+    const int e = tt / NF, fm = tt - e * NF, f = fm / Nfp;
+    const int64_t k = ok ? k0 + e : 0;
+    const int cn = A.conn[k * 4 + f];
+    const int nb = A.nbnode[k * NF + fm];
+    T.cn[u] = ok ? cn : CONN_ABSORB;
+    // masked arithmetic rather than a select, so the compiler keeps the
+    // node-table load unconditional (not behind a wait for cn)
+    const int64_t live = -(int64_t)(ok && cn >= 0);
+    T.gb[u] = ((int64_t)(cn >> 5) * 9 * Np + nb) & live;
+  }
+}
+
+// The block's own fields (16-byte vectors over its contiguous span, scalar
+// head and tail) and per-element data, loaded into registers: every load is
+// issued before any is waited for.
+template <int N, typename real, int BE>
+struct BlockLoad {
+  using SP = Span16<real>;
+  static constexpr int QV = (BE * 9 * Sz<N>::Np / SP::VW + kThreads - 1) / kThreads;
+  static constexpr int MV = (BE * DGW_META / 2 + kThreads - 1) / kThreads;
+  typename SP::vec q[QV];
+  real qh, qt;
+  double2 m[MV];
+};
+
+template <int N, typename real, int BE>
+__device__ __forceinline__ void block_loads(const StageArgs<real> &A, int64_t item,
+                                            int64_t nblk, BlockLoad<N, real, BE> &B) {
+  constexpr int Np = Sz<N>::Np;
+  using BL = BlockLoad<N, real, BE>;
+  using SP = typename BL::SP;
+  const int shot = (int)(item / nblk);
+  const int64_t k0 = (item - (int64_t)shot * nblk) * BE;
+  const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
+  const int tid = threadIdx.x;
+  // every load is unconditional, with out-of-range lanes clamped to an
+  // in-bounds index (their values are never stored): a load under a branch
+  // makes the compiler's wait counting conservative, and the neighbour
+  // gathers would wait for these loads
+  const bool ok = k0 < A.K;
+  const int64_t off = ok ? shot * A.shot_stride + k0 * 9 * Np : 0;
+  const SP sp(off, ok ? nE * 9 * Np : 1);
+  const real *src = A.q_in + off;
+  const int nv1 = sp.nv > 0 ? sp.nv - 1 : 0;
+  const typename SP::vec *sv = (const typename SP::vec *)(src + sp.hd);
+#pragma unroll
+  for (int u = 0; u < BL::QV; ++u) {
+    const int j = tid + u * kThreads;
+    B.q[u] = sv[j < sp.nv ? j : nv1];
+  }
+  B.qh = src[tid < sp.hd ? tid : 0];
+  B.qt = src[tid < sp.tl ? sp.hd + SP::VW * sp.nv + tid : 0];
+  const double2 *mv = (const double2 *)(A.meta + (ok ? k0 : 0) * DGW_META);
+#pragma unroll
+  for (int u = 0; u < BL::MV; ++u) {
+    const int j = tid + u * kThreads;
+    B.m[u] = mv[j < nE * DGW_META / 2 ? j : 0];
   }
 }
 
 template <int N, typename real, int BE, int V>
 __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t item,
-                                           int64_t nblk, const FaceTab<N, BE> &T) {
+                                           int64_t nblk, const FaceTab<N, BE> &T,
+                                           const BlockLoad<N, real, BE> &B) {
   constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Sz<N>::Nfp;
   constexpr int FI = (BE * NF + kThreads - 1) / kThreads;   // face items per thread
   // declared here (not passed in) so every access stays an LDS access
@@ -430,38 +481,41 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
   int oz;
   asm volatile("v_mov_b32 %0, 0" : "=v"(oz));
 
-  // ---- 1. all global reads of the item's fields are issued together ----
-  {
-    // fields (16-byte loads; the span starts wherever the block starts)
-    using SP = Span16<real>;
-    const int64_t off = shot * A.shot_stride + k0 * 9 * Np;
-    const SP sp(off, nE * 9 * Np);
-    const real *src = qin + k0 * 9 * Np;
-    if (tid < sp.hd) sq[tid] = src[tid];
-    const typename SP::vec *sv = (const typename SP::vec *)(src + sp.hd);
-    for (int t = tid; t < sp.nv; t += kThreads) {
-      const typename SP::vec v = sv[t];
-#pragma unroll
-      for (int l = 0; l < SP::VW; ++l) sq[sp.hd + SP::VW * t + l] = v[l];
-    }
-    if (tid < sp.tl) sq[sp.hd + SP::VW * sp.nv + tid] = src[sp.hd + SP::VW * sp.nv + tid];
-    // per-element data (48 doubles per element: 16-byte aligned)
-    const double2 *mv = (const double2 *)(A.meta + k0 * DGW_META);
-    for (int t = tid; t < nE * DGW_META / 2; t += kThreads) {
-      const double2 v = mv[t];
-      smeta[2 * t] = v.x;
-      smeta[2 * t + 1] = v.y;
-    }
-  }
-  // neighbour traces of this thread's face nodes go to registers
+  // ---- 1. all global reads of the item's fields are in flight together ----
+  // neighbour traces of this thread's face nodes go to registers; read
+  // unconditionally (boundary and idle face items have offset 0, an
+  // in-bounds read of the first element that is never used), so no branch
+  // makes the compiler wait on earlier loads
   real qp[FI][9];
   int cnv[FI];
 #pragma unroll
   for (int u = 0; u < FI; ++u) {
     cnv[u] = T.cn[u];
-    if (cnv[u] >= 0) {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) qp[u][c] = qin[T.gb[u] + c * Np];
+    for (int c = 0; c < 9; ++c) qp[u][c] = qin[T.gb[u] + c * Np];
+  }
+  // the block's own fields and per-element data (loads issued by
+  // block_loads) to LDS
+  {
+    using BL = BlockLoad<N, real, BE>;
+    using SP = typename BL::SP;
+    const SP sp(shot * A.shot_stride + k0 * 9 * Np, nE * 9 * Np);
+#pragma unroll
+    for (int u = 0; u < BL::QV; ++u) {
+      const int j = tid + u * kThreads;
+      if (j < sp.nv)
+#pragma unroll
+        for (int l = 0; l < SP::VW; ++l) sq[sp.hd + SP::VW * j + l] = B.q[u][l];
+    }
+    if (tid < sp.hd) sq[tid] = B.qh;
+    if (tid < sp.tl) sq[sp.hd + SP::VW * sp.nv + tid] = B.qt;
+#pragma unroll
+    for (int u = 0; u < BL::MV; ++u) {
+      const int j = tid + u * kThreads;
+      if (j < nE * DGW_META / 2) {
+        smeta[2 * j] = B.m[u].x;
+        smeta[2 * j + 1] = B.m[u].y;
+      }
     }
   }
   __syncthreads();
@@ -556,7 +610,9 @@ stage_kernel(StageArgs<real> A, int64_t nblk, int64_t total) {
   const int64_t item = xcd_item(blockIdx.x, total);
   FaceTab<N, BE> T;
   face_tables<N, real, BE>(A, item, nblk, T);
-  stage_item<N, real, BE, V>(A, item, nblk, T);
+  BlockLoad<N, real, BE> B;
+  block_loads<N, real, BE>(A, item, nblk, B);
+  stage_item<N, real, BE, V>(A, item, nblk, T, B);
 }
 
 // Persistent grid (a multiple of 8 work-groups) looping over the items;
@@ -572,7 +628,9 @@ stage_kernel_persistent(StageArgs<real> A, int64_t nblk, int64_t total) {
     FaceTab<N, BE> Tn;
     if (L + gridDim.x < total)
       face_tables<N, real, BE>(A, xcd_item(L + gridDim.x, total), nblk, Tn);
-    stage_item<N, real, BE, V>(A, item, nblk, T);
+    BlockLoad<N, real, BE> B;
+    block_loads<N, real, BE>(A, item, nblk, B);
+    stage_item<N, real, BE, V>(A, item, nblk, T, B);
     __syncthreads();   // LDS is reused by the next item
     T = Tn;
   }
