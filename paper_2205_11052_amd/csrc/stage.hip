@@ -134,36 +134,42 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
     const int e = cok ? col / 9 : 0, k = cok ? col - 9 * (col / 9) : 0;
     const real *qe = sq + e * 9 * Np;
     const double *gm = smeta + e * DGW_META;
-    // input-side coefficients of this column
-    real X[9];
-#pragma unroll
-    for (int u = 0; u < 9; ++u) X[u] = (real)gm[M_XINV + u];
+    // input-side coefficients of this column, c[a][m] = s_m X^-1[a][x_m],
+    // with the material factor s_m and the metric column x_m of each of
+    // the three combined fields f_m given per component k by packed tables
+    // (branch-free: the sixteen lanes of a column tile hold different k):
+    //   k = 0..2 (vx, vy, vz):   f = sigma row k, s = 1/rho, x = (0, 1, 2)
+    //   k = 3..5 (sxx..szz):      f = (vx, vy, vz), s = lambda + 2 mu on
+    //                             x = k - 3, lambda elsewhere, x = (0, 1, 2)
+    //   k = 6 (syz): f = (vy, vz), s = mu, x = (2, 1)
+    //   k = 7 (sxz): f = (vx, vz), s = mu, x = (2, 0)
+    //   k = 8 (sxy): f = (vx, vy), s = mu, x = (1, 0)
+    // fields (4 bits per k, m = 0, 1, 2)
+    constexpr uint64_t F0 = 0x001000783ull, F1 = 0x122111648ull, F2 = 0x210222567ull;
+    // metric columns (2 bits per k) and material factor ids (3 bits per k:
+    // 0 1/rho, 1 lambda + 2 mu, 2 lambda, 3 mu, 4 zero)
+    constexpr uint32_t X0 = 0x1a000u, X1 = 0x01555u, X2 = 0x2aaaau;
+    constexpr uint32_t S0 = 0x36d2200u, S1 = 0x36d1400u, S2 = 0x490a400u;
+    const int f0 = (int)((F0 >> (4 * k)) & 15), f1 = (int)((F1 >> (4 * k)) & 15),
+              f2 = (int)((F2 >> (4 * k)) & 15);
     const real ri = (real)gm[M_RHOINV], la = (real)gm[M_LAM], mu = (real)gm[M_MU];
     const real l2 = la + 2 * mu;
-    int f0, f1, f2;
+    auto fac = [&](uint32_t S) -> real {
+      const int id = (int)((S >> (3 * k)) & 7);
+      return id == 0 ? ri : id == 1 ? l2 : id == 2 ? la : id == 3 ? mu : (real)0;
+    };
+    const real s0 = fac(S0), s1 = fac(S1), s2 = fac(S2);
+    const int x0 = (int)((X0 >> (2 * k)) & 3), x1 = (int)((X1 >> (2 * k)) & 3),
+              x2 = (int)((X2 >> (2 * k)) & 3);
     real c[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const real x0 = X[3 * a], x1 = X[3 * a + 1], x2 = X[3 * a + 2];
-      switch (k) {
-        case 0: case 1: case 2:
-          c[a][0] = ri * x0; c[a][1] = ri * x1; c[a][2] = ri * x2; break;
-        case 3: c[a][0] = l2 * x0; c[a][1] = la * x1; c[a][2] = la * x2; break;
-        case 4: c[a][0] = la * x0; c[a][1] = l2 * x1; c[a][2] = la * x2; break;
-        case 5: c[a][0] = la * x0; c[a][1] = la * x1; c[a][2] = l2 * x2; break;
-        case 6: c[a][0] = mu * x2; c[a][1] = mu * x1; c[a][2] = 0; break;
-        case 7: c[a][0] = mu * x2; c[a][1] = mu * x0; c[a][2] = 0; break;
-        default: c[a][0] = mu * x1; c[a][1] = mu * x0; c[a][2] = 0; break;
-      }
-    }
-    // fields combined for each right-hand-side component (x, y, z parts)
-    switch (k) {
-      case 0: f0 = 3; f1 = 8; f2 = 7; break;   // (sxx, sxy, sxz)
-      case 1: f0 = 8; f1 = 4; f2 = 6; break;   // (sxy, syy, syz)
-      case 2: f0 = 7; f1 = 6; f2 = 5; break;   // (sxz, syz, szz)
-      case 6: f0 = 1; f1 = 2; f2 = 0; break;   // (vy, vz)
-      case 7: f0 = 0; f1 = 2; f2 = 1; break;   // (vx, vz)
-      default: f0 = 0; f1 = 1; f2 = 2; break;  // (vx, vy, vz)
+      const real r0 = (real)gm[M_XINV + 3 * a], r1 = (real)gm[M_XINV + 3 * a + 1],
+                 r2 = (real)gm[M_XINV + 3 * a + 2];
+      auto pick = [&](int x) { return x == 0 ? r0 : x == 1 ? r1 : r2; };
+      c[a][0] = s0 * pick(x0);
+      c[a][1] = s1 * pick(x1);
+      c[a][2] = s2 * pick(x2);
     }
     const real *q0 = qe + f0 * Np, *q1 = qe + f1 * Np, *q2 = qe + f2 * Np;
     v4 *ac = acc[ntl];
@@ -175,9 +181,11 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
       const real ca0 = c[a][0], ca1 = c[a][1], ca2 = c[a][2];
       const real *Ab = A.Avol + (size_t)a * KS * MT * 64 + lane + oz;
       for (int ks = 0; ks < KS; ++ks) {
-        const int j = 4 * ks + g;
-        real b = 0;
-        if (j < Np) b = ca0 * q0[j] + ca1 * q1[j] + ca2 * q2[j];
+        // rows past Np of the last k-step read a valid node and are zeroed
+        // (a select, not a branch, so the direction stays one basic block)
+        const int j = 4 * ks + g, jj = j < Np ? j : Np - 1;
+        real b = ca0 * q0[jj] + ca1 * q1[jj] + ca2 * q2[jj];
+        b = j < Np ? b : (real)0;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) ac[mt] = M::mma(Ab[(ks * MT + mt) * 64], b, ac[mt]);
       }
@@ -379,6 +387,7 @@ struct FaceTab {
   static constexpr int FI = (BE * 4 * Sz<N>::Nfp + kThreads - 1) / kThreads;
   int cn[FI];
   int64_t gb[FI];
+  int n1[FI];   // the face node's volume node in its own element
 };
 
 template <int N, typename real, int BE>
@@ -398,6 +407,7 @@ __device__ __forceinline__ void face_tables(const StageArgs<real> &A, int64_t it
     const int cn = A.conn[k * 4 + f];
     const int nb = A.nbnode[k * NF + fm];
     T.cn[u] = ok ? cn : CONN_ABSORB;
+    T.n1[u] = A.fmask[fm];
     // masked arithmetic rather than a select, so the compiler keeps the
     // node-table load unconditional (not behind a wait for cn)
     const int64_t live = -(int64_t)(ok && cn >= 0);
@@ -528,7 +538,7 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
     const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
     const double *g = smeta + e * DGW_META;
     const real *qe = sq + e * 9 * Np;
-    const int n1 = A.fmask[fm];
+    const int n1 = T.n1[u];
     real qm[9], p[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) qm[c] = qe[c * Np + n1];
