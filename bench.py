@@ -53,9 +53,9 @@ META_BYTES = 48 * 8 + 4 * 4        # per-element data + packed connectivity
 # is reported only while the kernel source hashes to the value it was
 # measured for and the same launch shape runs; otherwise traffic is null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "1bd38700595c0e6577a9298c387f5e6a176f389a5f826a646f89362e1989c630",
+    "kernel_source_sha256": "e2177220f81d640b17b4bc7d134356328db0333827f3d4232e8f734f093a8670",
     "launch_shape": (1, 7, 0),
-    "bytes_per_launch": 967936424,
+    "bytes_per_launch": 965221338,
 }
 
 
