@@ -251,6 +251,38 @@ def order6_form(torch, stream, w, steps, warmup):
     return out
 
 
+def general_mesh_form(torch, stream, w, steps, warmup, structured_ms):
+    """The workload's size (82944 elements, order 4, FP64) on a general mesh
+    (jittered vertices, random element and vertex numbering, random vertex
+    order per element) in three numberings: as generated (shuffled), Morton
+    and reverse Cuthill-McKee (dgw_order_elements).  Stage-kernel time with
+    the autotuned launch shape of each."""
+    import workloads as W
+    from paper_2205_11052_amd import order_elements, permute_mesh
+    g = W.general_mesh(w["mesh"]["n"], w["mesh"]["L"], seed=3)
+    K = g["etov"].shape[0]
+    Np = 35
+    out = {"elements": K, "structured_kernel_avg_ms": round(structured_ms, 5)}
+    for name in ("shuffled", "morton", "rcm"):
+        mesh = g if name == "shuffled" else permute_mesh(
+            g, order_elements(g["vxyz"], g["etov"], name))
+        rho, lam, mu, _ = W.layered_medium(W.element_centroids(mesh))
+        wg = dict(w, mesh=mesh, rho=rho, lam=lam, mu=mu)
+        with torch.cuda.stream(stream):
+            s = build_solver(wg, 64, stream=stream.cuda_stream)
+            sec, _ = timed_steps(torch, s, stream, steps, warmup)
+            kms, _ = kernel_avg_ms(s)
+            shape = s.shape
+            s.close()
+        out[name] = {
+            "value": round(9 * Np * K * 5 * steps / sec / 1e9, 3),
+            "kernel_avg_ms": round(kms, 5),
+            "hbm_frac": round(stage_bytes(K, Np, 8) / (kms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "vs_structured": round(structured_ms / kms, 3),
+            "launch_shape": list(shape)}
+    return out
+
+
 def cpu_baseline(w, steps=3):
     import torch
     from oracle import solver as O
@@ -380,6 +412,8 @@ def main():
             "note": "32 shots, one launch per stage over all shots, graph "
                     "replay; lengths 500-2000 steps, all active in the window"}
         forms["order6"] = order6_form(torch, stream, w, max(20, args.steps // 5), 2)
+        forms["general_mesh_fp64"] = general_mesh_form(
+            torch, stream, w, max(20, args.steps // 5), 2, kms)
         out["forms"] = forms
     if not args.no_adjoint:
         out["adjoint"] = adjoint_form(torch, stream)

@@ -163,6 +163,32 @@ int dgw_ref_nodes(int order, double *rst);
 int dgw_ref_operators(int order, double *Dr, double *Ds, double *Dt,
                       double *M, double *LIFT);
 
+/* Element ordering for gather locality (host only, no context needed).  The
+ * stage kernel works on blocks of consecutive elements and gives each XCD a
+ * contiguous range of blocks, so face neighbours close in the numbering are
+ * read from the same L2; this returns a numbering that keeps them close.
+ * perm [K] receives a permutation of 0..K-1: element i of the reordered mesh
+ * is input element perm[i].  The caller applies it to etov, face_bc, the
+ * per-element material and the fields before dgw_set_mesh (vertices are
+ * unchanged).
+ *   DGW_ORDER_MORTON: Morton (Z-order) curve of the element centroids,
+ *     21 bits per axis over the centroids' bounding box, bits interleaved
+ *     x, y, z from the least significant end, ties by input index;
+ *   DGW_ORDER_RCM: reverse Cuthill-McKee (Cuthill and McKee 1969, reversed
+ *     as by George 1971) on the face-adjacency graph, faces matched by their
+ *     sorted vertex triples with vertex_periodic_id as in dgw_set_mesh (may
+ *     be NULL); each connected component starts from an element of minimum
+ *     degree (ties by index), neighbours are queued by increasing degree
+ *     then index, and the breadth-first sequence is reversed.
+ * Deterministic.  DGW_EINVAL for null pointers, K or nvert <= 0, a vertex id
+ * outside [0, nvert) or an unknown method; DGW_EMESH (RCM) for a degenerate
+ * face or a vertex triple shared by more than two faces. */
+#define DGW_ORDER_MORTON 0
+#define DGW_ORDER_RCM 1
+int dgw_order_elements(int64_t nvert, const double *vxyz, int64_t K,
+                       const int32_t *etov, const int32_t *vertex_periodic_id,
+                       int method, int64_t *perm);
+
 /* Differentiation.  dgw_forward_checkpointed runs every shot from its current
  * state for nsteps steps, storing the state every ckpt_every steps in device
  * memory, and returns the misfit of each shot against d_obs

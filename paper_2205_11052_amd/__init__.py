@@ -8,7 +8,8 @@ the library's allocator hook) and streams.
 
 from ._lib import LibraryMissingError, library_path, load  # noqa: F401
 from .dgw import (Solver, ElasticMisfit, ref_nodes, ref_operators,  # noqa: F401
-                  DGWError)
+                  order_elements, permute_mesh, DGWError)
 
 __all__ = ["Solver", "ElasticMisfit", "ref_nodes", "ref_operators",
-           "DGWError", "LibraryMissingError", "load", "library_path"]
+           "order_elements", "permute_mesh", "DGWError",
+           "LibraryMissingError", "load", "library_path"]

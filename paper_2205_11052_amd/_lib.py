@@ -42,6 +42,8 @@ SIGNATURES = {
     "dgw_check_finite": (C.c_int, [_P]),
     "dgw_ref_nodes": (C.c_int, [C.c_int, _D]),
     "dgw_ref_operators": (C.c_int, [C.c_int, _D, _D, _D, _D, _D]),
+    "dgw_order_elements": (C.c_int, [_I64, _D, _I64, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32), C.c_int, _PI64]),
     "dgw_forward_checkpointed": (C.c_int, [_P, _I64, _I64, _D, _D]),
     "dgw_adjoint": (C.c_int, [_P, _D, _D, _D]),
     "dgw_autotune": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int),

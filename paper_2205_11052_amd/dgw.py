@@ -66,6 +66,42 @@ def ref_operators(order):
     return Dr, Ds, Dt, M, LIFT
 
 
+ORDER_METHODS = {"morton": 0, "rcm": 1}
+
+
+def order_elements(vxyz, etov, method="morton", vertex_periodic_id=None):
+    """Element numbering for gather locality (``dgw_order_elements``):
+    returns ``perm`` (int64 [K]) with element i of the reordered mesh being
+    input element perm[i]."""
+    lib = _lib.load()
+    vxyz = _f64(vxyz)
+    etov = np.ascontiguousarray(np.asarray(etov, dtype=np.int32))
+    pid = None
+    if vertex_periodic_id is not None:
+        pid = np.ascontiguousarray(np.asarray(vertex_periodic_id, np.int32))
+    if method not in ORDER_METHODS:
+        raise ValueError("method must be one of %s" % sorted(ORDER_METHODS))
+    perm = np.empty(etov.shape[0], dtype=np.int64)
+    rc = lib.dgw_order_elements(
+        vxyz.shape[0], _dptr(vxyz), etov.shape[0],
+        etov.ctypes.data_as(C.POINTER(C.c_int32)),
+        pid.ctypes.data_as(C.POINTER(C.c_int32)) if pid is not None else None,
+        ORDER_METHODS[method], perm.ctypes.data_as(C.POINTER(C.c_int64)))
+    if rc:
+        raise DGWError(rc, "dgw_order_elements")
+    return perm
+
+
+def permute_mesh(mesh, perm):
+    """The mesh dict with its elements renumbered by ``perm`` (etov and
+    face_bc rows; vertices unchanged)."""
+    out = dict(mesh)
+    out["etov"] = np.asarray(mesh["etov"])[perm]
+    if mesh.get("face_bc") is not None:
+        out["face_bc"] = np.asarray(mesh["face_bc"])[perm]
+    return out
+
+
 class Solver:
     """One dgw context: a mesh, a medium and ``nshots`` shots."""
 

@@ -11,7 +11,7 @@ All random draws use ``numpy.random.default_rng`` with fixed seeds so every
 input is reproducible.
 """
 
-from .mesh import kuhn_cube, lattice_node_coords, element_centroids
+from .mesh import kuhn_cube, general_mesh, lattice_node_coords, element_centroids
 from .medium import (layered_medium, blob_start_medium, homogeneous_medium,
                      lame_from_velocities)
 from .shots import (default_source, default_receivers, batched_shots,

@@ -95,6 +95,62 @@ def kuhn_cube(n, L=1.0, periodic=False, top_free_surface=True):
             "face_bc": face_bc, "n": n, "L": float(L), "h": h}
 
 
+# the 12 even permutations of (0, 1, 2, 3): relabelling an element's vertices
+# by one of them keeps its orientation positive
+EVEN_PERMS = [p for p in
+              [(a, b, c, d) for a in range(4) for b in range(4)
+               for c in range(4) for d in range(4)
+               if len({a, b, c, d}) == 4]
+              if sum(1 for i in range(4) for j in range(i + 1, 4)
+                     if p[i] > p[j]) % 2 == 0]
+
+
+def general_mesh(n, L=1.0, seed=0, jitter=0.15, top_free_surface=True):
+    """An unstructured-looking tetrahedral mesh of the cube [0, L]^3 from the
+    Kuhn split with every structured regularity removed (seeded):
+
+    * interior vertices moved by up to ``jitter * h`` per axis (boundary
+      vertices stay on their planes, so the domain and its boundary tags are
+      unchanged), so every element has its own affine map and normals;
+    * each element's local vertex order relabelled by a random even
+      permutation (orientation stays positive; face tags follow their faces),
+      so matched faces meet in every relative orientation;
+    * elements and vertex ids randomly renumbered.
+
+    Same keys as ``kuhn_cube`` plus ``elem_from_kuhn`` (the Kuhn element each
+    element came from) and ``vert_from_kuhn``.
+    """
+    m = kuhn_cube(n, L, periodic=False, top_free_surface=top_free_surface)
+    rng = np.random.default_rng(seed)
+    h = m["h"]
+    V = m["vxyz"].copy()
+    inner = np.all((V > 1e-9 * L) & (V < L - 1e-9 * L), axis=1)
+    V[inner] += rng.uniform(-jitter * h, jitter * h, size=(int(inner.sum()), 3))
+    etov = m["etov"].astype(np.int64)
+    bc = m["face_bc"].copy()
+    K = etov.shape[0]
+    sig = np.asarray(EVEN_PERMS)[rng.integers(0, len(EVEN_PERMS), size=K)]
+    etov = np.take_along_axis(etov, sig, axis=1)
+    bc = np.take_along_axis(bc, sig, axis=1)    # face f is opposite vertex f
+    pe = rng.permutation(K)
+    etov, bc = etov[pe], bc[pe]
+    pv = rng.permutation(V.shape[0])            # new id of old vertex v
+    Vn = np.empty_like(V)
+    Vn[pv] = V
+    etov = pv[etov]
+    a = Vn[etov[:, 1]] - Vn[etov[:, 0]]
+    b = Vn[etov[:, 2]] - Vn[etov[:, 0]]
+    d = Vn[etov[:, 3]] - Vn[etov[:, 0]]
+    det = np.einsum("ki,ki->k", a, np.cross(b, d))
+    if not np.all(det > 0):
+        raise ValueError("jitter too large: an element turned over")
+    inv_pv = np.empty_like(pv)
+    inv_pv[pv] = np.arange(pv.size)
+    return {"vxyz": Vn, "etov": etov.astype(np.int32), "vertex_periodic_id": None,
+            "face_bc": bc.astype(np.int8), "n": n, "L": float(L), "h": h,
+            "elem_from_kuhn": pe, "vert_from_kuhn": inv_pv}
+
+
 def element_centroids(mesh):
     """Mean of the 4 vertex coordinates of every element, [K, 3]."""
     return mesh["vxyz"][mesh["etov"]].mean(axis=1)
