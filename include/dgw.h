@@ -21,7 +21,9 @@
  *              face with P impedance sqrt(rho (lambda + 2 mu)) on the normal
  *              parts and S impedance sqrt(rho mu) on the tangential parts
  *              (Wilcox, Stadler, Burstedde, Ghattas, J. Comput. Phys. 229,
- *              2010), lifted to the element by the exact face mass matrices;
+ *              2010), optionally blended with the central flux
+ *              (dgw_set_flux), lifted to the element by the exact face mass
+ *              matrices;
  *   boundaries free surface (zero traction) and first-order absorbing
  *              (no incoming characteristic); periodic faces are ordinary
  *              neighbours;
@@ -189,7 +191,8 @@ int dgw_order_elements(int64_t nvert, const double *vxyz, int64_t K,
                        const int32_t *etov, const int32_t *vertex_periodic_id,
                        int method, int64_t *perm);
 
-/* Differentiation.  dgw_forward_checkpointed runs every shot from its current
+/* Differentiation (upwind flux only: DGW_ESTATE unless the flux weight of
+ * dgw_set_flux is 1).  dgw_forward_checkpointed runs every shot from its current
  * state for nsteps steps, storing the state every ckpt_every steps in device
  * memory, and returns the misfit of each shot against d_obs
  * [nshots][nrec][3][nsteps] (misfit [nshots], accumulated in FP64).
@@ -208,6 +211,16 @@ int dgw_adjoint(dgw_ctx *ctx, double *g_rho, double *g_lam, double *g_mu);
  * (either may be NULL); see dgw_set_launch. */
 int dgw_autotune(dgw_ctx *ctx, const char *cache_path, int *kernel,
                  int *elems_per_block, int *wgs_per_cu);
+
+/* Face flux.  The flux states are tau (t*, v*) + (1 - tau) ((t- + t+)/2,
+ * (v- + v+)/2): tau = 1 (the default) is the exact Riemann (upwind) flux,
+ * tau = 0 the central flux, values between a convex combination (the
+ * alpha-flux family of Hesthaven and Warburton 2008, section 2.2, with
+ * alpha = 1 - tau; boundary ghost states as for the upwind flux).  The
+ * central flux conserves the semi-discrete energy on meshes without
+ * boundaries.  DGW_EINVAL outside [0, 1].  dgw_forward_checkpointed and
+ * dgw_adjoint return DGW_ESTATE unless tau = 1. */
+int dgw_set_flux(dgw_ctx *ctx, double tau);
 
 /* Launch shape of the stage kernel.  kernel 0: one thread per (element,
  * node) with the block's fields and lifted fluxes staged in LDS; then

@@ -29,6 +29,12 @@ Semi-discrete strong form (nodal DG; Hesthaven and Warburton 2008):
       sigma_t += Fscale_f LIFT_f [lambda- (n.dv) I + mu- (dv n^T + n dv^T)].
 * boundary ghost states (Z+ = Z-): free surface v+ = v-, sigma+ = -sigma-
   (so t* = 0); absorbing v+ = 0, sigma+ = 0.
+* flux variant (P.flux_tau = tau in [0, 1], default 1): the states used are
+  tau (t*, v*) + (1 - tau) ((t- + t+)/2, (v- + v+)/2), i.e. a convex
+  combination of the upwind flux and the central flux (the alpha-flux family
+  of Hesthaven and Warburton, section 2.2 and chapter 6, with alpha =
+  1 - tau); the central flux conserves the semi-discrete energy on meshes
+  without boundaries, the upwind part dissipates it.
 
 Time stepping: five-stage fourth-order low-storage Runge-Kutta (Carpenter and
 Kennedy, NASA TM-109112, 1994): for i = 1..5,
@@ -112,6 +118,9 @@ class Problem:
         self.EToE_t = t(self.EToE)
         self.source = None
         self.receivers = None
+        # weight of the exact Riemann (upwind) flux; 1 - flux_tau goes to the
+        # central flux
+        self.flux_tau = 1.0
 
     # --- sources and receivers -------------------------------------------
     def set_source(self, xyz, f0, t0, amp=1.0, moment=(1, 1, 1, 0, 0, 0)):
@@ -208,8 +217,14 @@ def rhs(P, q, rho, lam, mu):
     tsT = (Zs_p * tmT + Zs_m * tpT + Zs_m * Zs_p * (vpT - vmT)) / (Zs_m + Zs_p)
     vsn = (Zp_m * vmn + Zp_p * vpn + tpn - tmn) / (Zp_m + Zp_p)
     vsT = (Zs_m * vmT + Zs_p * vpT + tpT - tmT) / (Zs_m + Zs_p)
-    dT = tsn * n + tsT - tm                                        # [K,3,4,Nfp]
-    dV = vsn * n + vsT - vm
+    # flux states: tau times the exact Riemann states plus (1 - tau) times
+    # the central (averaged) states; tau = 1 is the upwind flux, tau = 0
+    # the central one (boundary ghost states as above in both)
+    tau = P.flux_tau
+    tS = tau * (tsn * n + tsT) + (1.0 - tau) * 0.5 * (tm + tp)
+    vS = tau * (vsn * n + vsT) + (1.0 - tau) * 0.5 * (vm + vp)
+    dT = tS - tm                                                   # [K,3,4,Nfp]
+    dV = vS - vm
     ndv = (n * dV).sum(dim=1)                                      # [K,4,Nfp]
     lm = lam[:, None, None]
     mm = mu[:, None, None]

@@ -141,6 +141,8 @@ int dgw_forward_checkpointed(dgw_ctx *c, int64_t nsteps, int64_t every,
     return c->fail(DGW_ESTATE, "mesh, material and dt must be set first");
   if (nsteps < 1 || every < 1) return c->fail(DGW_EINVAL, "nsteps and ckpt_every must be >= 1");
   if (!d_obs || !misfit) return c->fail(DGW_EINVAL, "null d_obs or misfit");
+  if (c->flux_tau != 1.0)
+    return c->fail(DGW_ESTATE, "the adjoint supports the upwind flux only (flux weight 1)");
   for (int s = 0; s < c->nshots; ++s) {
     if (c->h_step[s] != 0)
       return c->fail(DGW_ESTATE, "every shot must start at step 0 (set its fields first)");
@@ -220,6 +222,8 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
   if (!c) return DGW_EINVAL;
   if (!c->adj || !c->adj->ready)
     return c->fail(DGW_ESTATE, "call dgw_forward_checkpointed first");
+  if (c->flux_tau != 1.0)
+    return c->fail(DGW_ESTATE, "the adjoint supports the upwind flux only (flux weight 1)");
   if (!g_rho || !g_lam || !g_mu) return c->fail(DGW_EINVAL, "null gradient output");
   dgw_ctx::Adjoint *a = c->adj;
   int rc;

@@ -826,6 +826,15 @@ int dgw_set_launch(dgw_ctx *c, int kernel, int elems_per_block, int wgs_per_cu) 
   return DGW_OK;
 }
 
+int dgw_set_flux(dgw_ctx *c, double tau) {
+  if (!c) return DGW_EINVAL;
+  if (!(tau >= 0.0 && tau <= 1.0))
+    return c->fail(DGW_EINVAL, "flux weight must lie in [0, 1]");
+  c->flux_tau = tau;
+  c->invalidate_graph();
+  return DGW_OK;
+}
+
 int dgw_enable_timing(dgw_ctx *c, int on) {
   if (!c) return DGW_EINVAL;
   c->timing = on != 0;

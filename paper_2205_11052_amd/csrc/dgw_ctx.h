@@ -34,6 +34,7 @@ struct dgw_ctx {
   dgw::MeshData mesh;
   bool have_mesh = false, have_mat = false, have_dt = false;
   double dt = 0;
+  double flux_tau = 1.0;            // upwind weight of the face flux
   std::vector<double> rho, lam, mu;
 
   // device data
@@ -126,6 +127,7 @@ inline void stage_args(const dgw_ctx *c, dgw::StageArgs<real> &a, const void *in
   a.src_elem = c->d_src_elem;
   a.src_vec = c->d_src_vec;
   a.src_par = c->d_src_par;
+  a.ftau = (real)c->flux_tau;
   a.rk_a = dgw::rk_a()[stage];
   a.rk_b = dgw::rk_b()[stage];
   a.rk_c = dgw::rk_c()[stage];

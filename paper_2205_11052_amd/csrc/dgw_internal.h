@@ -87,6 +87,7 @@ struct StageArgs {
   const int32_t *src_elem;      // [S] (-1: none)
   const double *src_vec;        // [S][Np]
   const double *src_par;        // [S][10]: moment[6], f0, t0, amp, unused
+  real ftau;                    // weight of the upwind flux (1 - ftau: central)
   double rk_a, rk_b, rk_c, dt;
 };
 

@@ -18,7 +18,8 @@
 //      a per-face-node table, so no load waits on a table lookup) into
 //      registers;
 //   2. one thread per (element, face node): exact Riemann flux in jump form
-//      from the own trace (LDS) and the neighbour's (registers); six lifted
+//      (optionally blended with the central flux) from the own trace (LDS)
+//      and the neighbour's (registers); six lifted
 //      quantities go to LDS: the velocity flux and the velocity change dv,
 //      both times Fscale (the stress flux is lambda (n.dv) I + mu (dv n^T +
 //      n dv^T), n constant per face, so it is formed after lifting dv);
@@ -575,27 +576,37 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
     const real kTy = (dty - dtn * ny + zsn * (dvy - dvn * ny)) * izs;
     const real kTz = (dtz - dtn * nz + zsn * (dvz - dvn * nz)) * izs;
     const real ri = (real)g[M_RHOINV], fs = (real)g[M_FSCALE + f];
-    // velocity flux (t* - t-)/rho and the velocity change dv = v* - v-; the
-    // stress flux is lambda (n.dv) I + mu (dv n^T + n dv^T) with n constant
-    // on the face, so lifting dv is enough for all six stress components
+    // traction change t* - t- and velocity change dv = v* - v- of the flux
+    // states: tu times the exact Riemann states' plus (1 - tu) times the
+    // central states' (half the jumps); tu = 1 (upwind) leaves exactly the
+    // Riemann terms (1 x + 0 = x)
+    const real tu = A.ftau, hc = ((real)1 - tu) * (real)0.5;
+    const real wx = tu * (zp * kn * nx + zs * kTx) + hc * dtx;
+    const real wy = tu * (zp * kn * ny + zs * kTy) + hc * dty;
+    const real wz = tu * (zp * kn * nz + zs * kTz) + hc * dtz;
+    const real ux = tu * (kn * nx + kTx) + hc * dvx;
+    const real uy = tu * (kn * ny + kTy) + hc * dvy;
+    const real uz = tu * (kn * nz + kTz) + hc * dvz;
+    // velocity flux (t* - t-)/rho and the velocity change dv; the stress
+    // flux is lambda (n.dv) I + mu (dv n^T + n dv^T) with n constant on the
+    // face, so lifting dv is enough for all six stress components
     if constexpr (V == 0) {
       real *d = sfl + (e * NF + fm) * 6;
-      d[0] = fs * (zp * kn * nx + zs * kTx) * ri;
-      d[1] = fs * (zp * kn * ny + zs * kTy) * ri;
-      d[2] = fs * (zp * kn * nz + zs * kTz) * ri;
-      d[3] = fs * (kn * nx + kTx);
-      d[4] = fs * (kn * ny + kTy);
-      d[5] = fs * (kn * nz + kTz);
+      d[0] = fs * wx * ri;
+      d[1] = fs * wy * ri;
+      d[2] = fs * wz * ri;
+      d[3] = fs * ux;
+      d[4] = fs * uy;
+      d[5] = fs * uz;
     } else {
       // all nine lifted components, field-major (the GEMM's data side)
       const real la = (real)g[M_LAM], mu = (real)g[M_MU];
-      const real Dvx = fs * (kn * nx + kTx), Dvy = fs * (kn * ny + kTy),
-                 Dvz = fs * (kn * nz + kTz);
+      const real Dvx = fs * ux, Dvy = fs * uy, Dvz = fs * uz;
       const real ndv = nx * Dvx + ny * Dvy + nz * Dvz;
       real *d = sfl + e * 9 * NF + fm;
-      d[0 * NF] = fs * (zp * kn * nx + zs * kTx) * ri;
-      d[1 * NF] = fs * (zp * kn * ny + zs * kTy) * ri;
-      d[2 * NF] = fs * (zp * kn * nz + zs * kTz) * ri;
+      d[0 * NF] = fs * wx * ri;
+      d[1 * NF] = fs * wy * ri;
+      d[2 * NF] = fs * wz * ri;
       d[3 * NF] = la * ndv + 2 * mu * Dvx * nx;
       d[4 * NF] = la * ndv + 2 * mu * Dvy * ny;
       d[5 * NF] = la * ndv + 2 * mu * Dvz * nz;

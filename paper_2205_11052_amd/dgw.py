@@ -291,6 +291,10 @@ class Solver:
         self._check(self.lib.dgw_set_launch(self._ctx, int(kernel), int(elems),
                                             int(wgs_per_cu)), "dgw_set_launch")
 
+    def set_flux(self, tau=1.0):
+        """Upwind weight of the face flux (1 upwind, 0 central)."""
+        self._check(self.lib.dgw_set_flux(self._ctx, float(tau)), "dgw_set_flux")
+
     def enable_timing(self, on=True):
         self._check(self.lib.dgw_enable_timing(self._ctx, 1 if on else 0),
                     "dgw_enable_timing")
