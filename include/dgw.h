@@ -101,8 +101,15 @@ int dgw_set_mesh(dgw_ctx *ctx, int64_t nvert, const double *vxyz, int64_t K,
                  const int32_t *etov, const int32_t *vertex_periodic_id,
                  const int8_t *face_bc);
 
-/* Per-element density and Lame parameters [K]; requires rho > 0, mu > 0,
- * lambda + 2 mu / 3 > 0 and finite values (DGW_EINVAL otherwise). */
+/* Per-element density and Lame parameters [K]; requires rho > 0, mu >= 0,
+ * lambda + 2 mu / 3 > 0 and finite values (DGW_EINVAL otherwise).  mu = 0
+ * makes the element a fluid (acoustic; its stress is meant to be isotropic,
+ * -p I): S impedance zero, coupled to solid neighbours through the same
+ * Riemann states (the solid's tangential traction acts on a slip
+ * interface), and with no tangential coupling where both sides are fluid.
+ * dgw_energy counts a fluid element's isotropic stress only,
+ * tr^T M tr / (9 lambda).  The gradient (dgw_forward_checkpointed,
+ * dgw_adjoint) is not defined with fluid elements: DGW_ESTATE. */
 int dgw_set_material(dgw_ctx *ctx, const double *rho, const double *lam,
                      const double *mu);
 
@@ -150,7 +157,8 @@ int dgw_shot_steps(dgw_ctx *ctx, int shot, int64_t *steps);
 
 /* Discrete energy of one shot,
  * E = 1/2 sum_k J_k [rho v^T M v + sigma^T (S (x) M) sigma] with S the
- * isotropic compliance, accumulated in FP64 on the device. */
+ * isotropic compliance (fluid elements: tr^T M tr / (9 lambda) in place of
+ * the stress term), accumulated in FP64 on the device. */
 int dgw_energy(dgw_ctx *ctx, int shot, double *E);
 
 /* DGW_ENONFINITE if any field value of any shot is NaN or infinite. */

@@ -29,6 +29,10 @@ Semi-discrete strong form (nodal DG; Hesthaven and Warburton 2008):
       sigma_t += Fscale_f LIFT_f [lambda- (n.dv) I + mu- (dv n^T + n dv^T)].
 * boundary ghost states (Z+ = Z-): free surface v+ = v-, sigma+ = -sigma-
   (so t* = 0); absorbing v+ = 0, sigma+ = 0.
+* fluid elements (mu = 0, acoustic; row f3): Zs = 0, so the tangential
+  states above are well defined whenever one side is solid (the solid's
+  tangential traction acts on a slip interface); where both sides are fluid
+  (Zs- + Zs+ = 0) there is no tangential coupling: t*_T = t-_T, v*_T = v-_T.
 * flux variant (P.flux_tau = tau in [0, 1], default 1): the states used are
   tau (t*, v*) + (1 - tau) ((t- + t+)/2, (v- + v+)/2), i.e. a convex
   combination of the upwind flux and the central flux (the alpha-flux family
@@ -50,7 +54,10 @@ point).
 Receivers: after every step, trace[r, c, n] = l(r_r) . v_c(k_r), c = x, y, z.
 
 Energy: E = 1/2 sum_k J_k [ rho v.Mv + (1/(2 mu)) (sum_diag s^T M s
-         + 2 sum_offdiag s^T M s) - lambda / (2 mu (3 lambda + 2 mu)) tr^T M tr ].
+         + 2 sum_offdiag s^T M s) - lambda / (2 mu (3 lambda + 2 mu)) tr^T M tr ];
+for a fluid element (mu = 0) the potential term is the isotropic part,
+tr^T M tr / (9 lambda) (the mu -> 0 limit of the above for isotropic
+stress; a fluid's deviatoric stress does not evolve).
 
 Misfit: J = 1/2 dt sum_n sum_r sum_c (trace - d)^2.
 """
@@ -214,9 +221,15 @@ def rhs(P, q, rho, lam, mu):
     tmn, tmT = split(tm)
     tpn, tpT = split(tp)
     tsn = (Zp_p * tmn + Zp_m * tpn + Zp_m * Zp_p * (vpn - vmn)) / (Zp_m + Zp_p)
-    tsT = (Zs_p * tmT + Zs_m * tpT + Zs_m * Zs_p * (vpT - vmT)) / (Zs_m + Zs_p)
+    # fluid on both sides (mu = 0, Zs- + Zs+ = 0): no tangential coupling,
+    # the tangential states stay the own ones
+    zs_sum = Zs_m + Zs_p
+    solid = (zs_sum.real if zs_sum.is_complex() else zs_sum) > 0
+    zs_den = torch.where(solid, zs_sum, torch.ones_like(zs_sum))
+    tsT = torch.where(solid, (Zs_p * tmT + Zs_m * tpT + Zs_m * Zs_p * (vpT - vmT)) / zs_den,
+                      tmT)
     vsn = (Zp_m * vmn + Zp_p * vpn + tpn - tmn) / (Zp_m + Zp_p)
-    vsT = (Zs_m * vmT + Zs_p * vpT + tpT - tmT) / (Zs_m + Zs_p)
+    vsT = torch.where(solid, (Zs_m * vmT + Zs_p * vpT + tpT - tmT) / zs_den, vmT)
     # flux states: tau times the exact Riemann states plus (1 - tau) times
     # the central (averaged) states; tau = 1 is the upwind flux, tau = 0
     # the central one (boundary ghost states as above in both)
@@ -292,8 +305,12 @@ def energy(P, q, rho, lam, mu):
     diag = sum(quad(q[:, c], q[:, c]) for c in (SXX, SYY, SZZ))
     off = sum(quad(q[:, c], q[:, c]) for c in (SYZ, SXZ, SXY))
     tr = q[:, SXX] + q[:, SYY] + q[:, SZZ]
-    pot = (diag + 2.0 * off) / (2.0 * mu) \
-        - lam / (2.0 * mu * (3.0 * lam + 2.0 * mu)) * quad(tr, tr)
+    trq = quad(tr, tr)
+    fluid = (mu.real if mu.is_complex() else mu) == 0
+    mus = torch.where(fluid, torch.ones_like(mu), mu)
+    elastic = (diag + 2.0 * off) / (2.0 * mus) \
+        - lam / (2.0 * mus * (3.0 * lam + 2.0 * mus)) * trq
+    pot = torch.where(fluid, trq / (9.0 * lam), elastic)
     return 0.5 * torch.sum(P.J.to(q.dtype) * (rho * kin + pot))
 
 

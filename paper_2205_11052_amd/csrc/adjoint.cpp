@@ -143,6 +143,9 @@ int dgw_forward_checkpointed(dgw_ctx *c, int64_t nsteps, int64_t every,
   if (!d_obs || !misfit) return c->fail(DGW_EINVAL, "null d_obs or misfit");
   if (c->flux_tau != 1.0)
     return c->fail(DGW_ESTATE, "the adjoint supports the upwind flux only (flux weight 1)");
+  for (int64_t k = 0; k < c->mesh.K; ++k)
+    if (c->mu[k] == 0.0)
+      return c->fail(DGW_ESTATE, "the gradient is not defined with fluid (mu = 0) elements");
   for (int s = 0; s < c->nshots; ++s) {
     if (c->h_step[s] != 0)
       return c->fail(DGW_ESTATE, "every shot must start at step 0 (set its fields first)");

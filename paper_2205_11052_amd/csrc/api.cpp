@@ -329,7 +329,9 @@ int dgw_ctx::material_meta() {
       m[M_ZPNB + f] = zp;
       m[M_ZSNB + f] = zs;
       m[M_IZPS + f] = 1.0 / (m[M_ZP] + zp);
-      m[M_IZSS + f] = 1.0 / (m[M_ZS] + zs);
+      // both sides fluid (mu = 0): no tangential coupling (the kernel's
+      // tangential Riemann amplitude is multiplied by this factor)
+      m[M_IZSS + f] = m[M_ZS] + zs > 0 ? 1.0 / (m[M_ZS] + zs) : 0.0;
     }
   }
   return upload(d_meta, g.data(), sizeof(double) * g.size());
@@ -511,7 +513,7 @@ int dgw_set_material(dgw_ctx *c, const double *rho, const double *lam,
     if (!std::isfinite(rho[k]) || !std::isfinite(lam[k]) || !std::isfinite(mu[k]))
       return c->fail(DGW_EINVAL, "non-finite material at element " + std::to_string(k));
     if (!(rho[k] > 0)) return c->fail(DGW_EINVAL, "rho <= 0 at element " + std::to_string(k));
-    if (!(mu[k] > 0)) return c->fail(DGW_EINVAL, "mu <= 0 at element " + std::to_string(k));
+    if (!(mu[k] >= 0)) return c->fail(DGW_EINVAL, "mu < 0 at element " + std::to_string(k));
     if (!(lam[k] + 2.0 * mu[k] / 3.0 > 0))
       return c->fail(DGW_EINVAL, "lambda + 2 mu / 3 <= 0 at element " + std::to_string(k));
   }

@@ -57,9 +57,13 @@ energy_kernel(const real *q, int64_t K, int Np, const double *meta,
       }
     const double rho = g[47], la = g[M_LAM], mu = g[M_MU];
     const double kin = quad[0] + quad[1] + quad[2];
-    const double pot = (quad[3] + quad[4] + quad[5] +
-                        2.0 * (quad[6] + quad[7] + quad[8])) / (2.0 * mu) -
-                       la / (2.0 * mu * (3.0 * la + 2.0 * mu)) * trq;
+    // a fluid element (mu = 0) stores only the isotropic part,
+    // tr^T M tr / (9 lambda): the mu -> 0 limit for isotropic stress
+    const double pot =
+        mu > 0.0 ? (quad[3] + quad[4] + quad[5] + 2.0 * (quad[6] + quad[7] + quad[8])) /
+                           (2.0 * mu) -
+                       la / (2.0 * mu * (3.0 * la + 2.0 * mu)) * trq
+                 : trq / (9.0 * la);
     acc += 0.5 * g[M_J] * (rho * kin + pot);
   }
   red[threadIdx.x] = acc;
