@@ -129,3 +129,25 @@ def test_full_size_general_mesh_fp64():
         terr = rel_l2(s.read_traces(0), tr_ora)
         say("full general mesh shape %s fields %.3e traces %.3e" % (shape, err, terr))
         assert err <= FP64_TOL and terr <= FP64_TOL
+
+
+def test_mesh_read_from_file_matches_oracle(tmp_path):
+    """A general mesh written to an MSH 2.2 file and read back runs to the
+    FP64 bar against the oracle on the read mesh."""
+    from paper_2205_11052_amd.meshio import read_msh, write_msh
+    p = tmp_path / "general.msh"
+    write_msh(p, W.general_mesh(4, 2.0, seed=33))
+    mesh = read_msh(p, bc_map={1: 1, 2: 2})
+    K = mesh["etov"].shape[0]
+    say("case mesh from file K=%d" % K)
+    rho, lam, mu = _random_medium(K, 44)
+    P = oracle_problem(mesh, 4)
+    dt = P.suggest_dt(rho, lam, mu, 0.5)
+    q0 = random_fields(K, P.Np, 45)
+    s = gpu_solver(mesh, 4, rho, lam, mu, dt, kernel=1)
+    s.set_fields(0, q0)
+    s.step(5)
+    q_ora, _ = oracle_run(P, q0, rho, lam, mu, dt, 5)
+    err = rel_l2(s.get_fields(0), q_ora)
+    say("mesh from file fields %.3e" % err)
+    assert err <= FP64_TOL
