@@ -28,7 +28,7 @@ struct dgw_ctx::Adjoint {
   int64_t *d_aux = nullptr;     // per-shot step used by recomputation
   // adjoint operators (row-major D, LIFT) and tables
   void *d_Dr = nullptr, *d_Ds = nullptr, *d_Dt = nullptr, *d_LIFT = nullptr;
-  int32_t *d_facepos = nullptr, *d_nbface = nullptr;
+  int32_t *d_facepos = nullptr;
 };
 
 void dgw_ctx::free_adjoint() {
@@ -41,7 +41,6 @@ void dgw_ctx::free_adjoint() {
   dfree(adj->d_Dt);
   dfree(adj->d_LIFT);
   dfree(adj->d_facepos);
-  dfree(adj->d_nbface);
   delete adj;
   adj = nullptr;
 }
@@ -76,12 +75,8 @@ int upload_adjoint_tables(dgw_ctx *c) {
   for (int f = 0; f < 4; ++f)
     for (int m = 0; m < Nfp; ++m) fp[f * Np + c->R.fmask[f * Nfp + m]] = m;
   a->d_facepos = (int32_t *)c->dalloc(sizeof(int32_t) * fp.size());
-  a->d_nbface = (int32_t *)c->dalloc(sizeof(int32_t) * c->mesh.nbface.size());
-  if (!a->d_facepos || !a->d_nbface)
-    return c->fail(DGW_ENOMEM, "device allocation failed (adjoint tables)");
-  if ((rc = c->upload(a->d_facepos, fp.data(), sizeof(int32_t) * fp.size()))) return rc;
-  return c->upload(a->d_nbface, c->mesh.nbface.data(),
-                   sizeof(int32_t) * c->mesh.nbface.size());
+  if (!a->d_facepos) return c->fail(DGW_ENOMEM, "device allocation failed (adjoint tables)");
+  return c->upload(a->d_facepos, fp.data(), sizeof(int32_t) * fp.size());
 }
 
 template <typename real>
@@ -94,8 +89,8 @@ void fill_adj(dgw_ctx *c, AdjArgs<real> &a, const void *q, void *lq, void *lr,
   a.grad = grad;
   a.meta = c->d_meta;
   a.conn = c->d_conn;
-  a.nbtab = c->d_nbtab;
-  a.nbface = c->adj->d_nbface;
+  a.nbnode = c->d_nbnode;
+  a.nbfnode = c->d_nbfnode;
   a.DrT = (const real *)c->d_DrT;
   a.DsT = (const real *)c->d_DsT;
   a.DtT = (const real *)c->d_DtT;

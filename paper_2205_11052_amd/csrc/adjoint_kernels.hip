@@ -110,32 +110,58 @@ __global__ void __launch_bounds__(kT) adj_lift_kernel(AdjArgs<real> A) {
   __shared__ real sw[BE * 9 * Np];
   __shared__ double sfs[BE * 4];
   const int shot = blockIdx.y;
-  const int64_t step = A.shot_step[shot];
-  if (step >= A.shot_len[shot]) return;
   const int64_t k0 = (int64_t)blockIdx.x * BE;
-  if (k0 >= A.K) return;
+  if (k0 >= A.K) return;   // never taken (the grid covers the mesh exactly)
   const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
   const int64_t off = shot * A.shot_stride + k0 * 9 * Np;
   const real b = (real)A.rk_b;
+  const int tid = threadIdx.x;
   {
     // w = lam_r + b lam_q over the block's contiguous span (16-byte loads)
+    // and Fscale, every load issued (unconditionally, clamped) before any
+    // is waited for
     using SP = Span16<real>;
+    using vec = typename SP::vec;
+    constexpr int QV = (BE * 9 * Np / SP::VW + kT - 1) / kT;
+    constexpr int FV = (BE * 4 + kT - 1) / kT;
     const SP sp(off, nE * 9 * Np);
     const real *lr = A.lam_r + off, *lq = A.lam_q + off;
-    const int tid = threadIdx.x;
-    if (tid < sp.hd) sw[tid] = lr[tid] + b * lq[tid];
-    for (int t = tid; t < sp.nv; t += kT) {
-      const int o = sp.hd + SP::VW * t;
-      const typename SP::vec x = *(const typename SP::vec *)(lr + o),
-                             y = *(const typename SP::vec *)(lq + o);
+    const int nv1 = sp.nv > 0 ? sp.nv - 1 : 0;
+    vec vr[QV], vl[QV];
 #pragma unroll
-      for (int l = 0; l < SP::VW; ++l) sw[o + l] = x[l] + b * y[l];
+    for (int u = 0; u < QV; ++u) {
+      const int j = tid + u * kT, jj = j < sp.nv ? j : nv1;
+      vr[u] = ((const vec *)(lr + sp.hd))[jj];
+      vl[u] = ((const vec *)(lq + sp.hd))[jj];
     }
-    const int o = sp.hd + SP::VW * sp.nv;
-    if (tid < sp.tl) sw[o + tid] = lr[o + tid] + b * lq[o + tid];
+    const int ih = tid < sp.hd ? tid : 0;
+    const int it = tid < sp.tl ? sp.hd + SP::VW * sp.nv + tid : 0;
+    const real hr = lr[ih], hl = lq[ih], tr_ = lr[it], tl_ = lq[it];
+    double fsv[FV];
+#pragma unroll
+    for (int u = 0; u < FV; ++u) {
+      const int t = tid + u * kT, tt = t < nE * 4 ? t : 0;
+      fsv[u] = A.meta[(k0 + tt / 4) * DGW_META + M_FSCALE + (tt & 3)];
+    }
+    const int64_t step = A.shot_step[shot];
+    if (step >= A.shot_len[shot]) return;   // uniform per work-group
+#pragma unroll
+    for (int u = 0; u < QV; ++u) {
+      const int j = tid + u * kT;
+      if (j < sp.nv) {
+        const int o = sp.hd + SP::VW * j;
+#pragma unroll
+        for (int l = 0; l < SP::VW; ++l) sw[o + l] = vr[u][l] + b * vl[u][l];
+      }
+    }
+    if (tid < sp.hd) sw[tid] = hr + b * hl;
+    if (tid < sp.tl) sw[it] = tr_ + b * tl_;
+#pragma unroll
+    for (int u = 0; u < FV; ++u) {
+      const int t = tid + u * kT;
+      if (t < nE * 4) sfs[t] = fsv[u];
+    }
   }
-  for (int t = threadIdx.x; t < nE * 4; t += kT)
-    sfs[t] = A.meta[(k0 + t / 4) * DGW_META + M_FSCALE + (t & 3)];
   __syncthreads();
   real *zb = A.zbuf + (shot * A.K + k0) * 9 * NF;
   for (int t = threadIdx.x; t < nE * NF; t += kT) {
@@ -164,13 +190,10 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
   __shared__ double sg[BE * 3 * NF];
   __shared__ double sgv[BE * 3 * Np];
   __shared__ double smeta[BE * DGW_META];
-  __shared__ int scn[BE * 4];
 
   const int shot = blockIdx.y;
-  const int64_t step = A.shot_step[shot];
-  if (step >= A.shot_len[shot]) return;
   const int64_t k0 = (int64_t)blockIdx.x * BE;
-  if (k0 >= A.K) return;
+  if (k0 >= A.K) return;   // never taken (the grid covers the mesh exactly)
   const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
   const int64_t soff = shot * A.shot_stride;
   const real *__restrict__ q = A.q + soff;
@@ -180,78 +203,141 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
   const real b = (real)A.rk_b;
   const int tid = threadIdx.x;
 
-  {
-    // w = lam_r + b lam_q and the stage input q over the block's contiguous
-    // span (16-byte loads)
-    using SP = Span16<real>;
-    const SP sp(soff + k0 * 9 * Np, nE * 9 * Np);
-    const real *lrb = lr + k0 * 9 * Np, *lqb = lq + k0 * 9 * Np, *qb = q + k0 * 9 * Np;
-    if (tid < sp.hd) {
-      sw[tid] = lrb[tid] + b * lqb[tid];
-      sq[tid] = qb[tid];
+  // ---- every global read of the block is issued before any is waited
+  //      for; all unconditional, with out-of-range lanes clamped to
+  //      in-bounds indices (a load under a branch makes the compiler wait on
+  //      it, and vmcnt completes loads in order)
+  constexpr int FI = (BE * NF + kT - 1) / kT;   // face items per thread
+  // level 1: this thread's face tables and own z
+  int cnv[FI], n1v[FI], n2v[FI], f2v[FI];
+  real zo[FI][9];
+#pragma unroll
+  for (int u = 0; u < FI; ++u) {
+    const int t = tid + u * kT;
+    const bool ok = t < nE * NF;
+    const int tt = ok ? t : 0;
+    const int e = tt / NF, fm = tt - e * NF, f = fm / Nfp;
+    const int64_t k = k0 + e;
+    const int cn = A.conn[k * 4 + f];
+    cnv[u] = ok ? cn : CONN_ABSORB;
+    n1v[u] = A.fmask[fm];
+    n2v[u] = A.nbnode[k * NF + fm];
+    f2v[u] = A.nbfnode[k * NF + fm];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) zo[u][c] = zb[(k * 9 + c) * NF + fm];
+  }
+  // the block's w = lam_r + b lam_q and stage input q (16-byte vectors over
+  // its contiguous span) and per-element data
+  using SP = Span16<real>;
+  using vec = typename SP::vec;
+  constexpr int QV = (BE * 9 * Np / SP::VW + kT - 1) / kT;
+  constexpr int MV = (BE * DGW_META / 2 + kT - 1) / kT;
+  const SP sp(soff + k0 * 9 * Np, nE * 9 * Np);
+  const real *lrb = lr + k0 * 9 * Np, *lqb = lq + k0 * 9 * Np, *qb = q + k0 * 9 * Np;
+  const int nv1 = sp.nv > 0 ? sp.nv - 1 : 0;
+  vec vr[QV], vl[QV], vq[QV];
+#pragma unroll
+  for (int u = 0; u < QV; ++u) {
+    const int j = tid + u * kT, jj = j < sp.nv ? j : nv1;
+    vr[u] = ((const vec *)(lrb + sp.hd))[jj];
+    vl[u] = ((const vec *)(lqb + sp.hd))[jj];
+    vq[u] = ((const vec *)(qb + sp.hd))[jj];
+  }
+  const int ih = tid < sp.hd ? tid : 0;
+  const int it = tid < sp.tl ? sp.hd + SP::VW * sp.nv + tid : 0;
+  const real hr = lrb[ih], hl = lqb[ih], hq = qb[ih];
+  const real tr_ = lrb[it], tl_ = lqb[it], tq = qb[it];
+  const double2 *mv = (const double2 *)(A.meta + k0 * DGW_META);
+  double2 mm[MV];
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    const int j = tid + u * kT;
+    mm[u] = mv[j < nE * DGW_META / 2 ? j : 0];
+  }
+  const int64_t step = A.shot_step[shot];
+  if (step >= A.shot_len[shot]) return;   // uniform per work-group
+  // level 2: the neighbour's trace, z at the matched face node and material
+  // (element 0 where the face has no neighbour; never used)
+  real qp[FI][9], zn[FI][9], gn[FI][5];
+#pragma unroll
+  for (int u = 0; u < FI; ++u) {
+    const int64_t nb = cnv[u] >= 0 ? (int64_t)(cnv[u] >> 5) : 0;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      qp[u][c] = q[(nb * 9 + c) * Np + n2v[u]];
+      zn[u][c] = zb[(nb * 9 + c) * NF + f2v[u]];
     }
-    for (int t = tid; t < sp.nv; t += kT) {
-      const int o = sp.hd + SP::VW * t;
-      const typename SP::vec x = *(const typename SP::vec *)(lrb + o),
-                             y = *(const typename SP::vec *)(lqb + o),
-                             z = *(const typename SP::vec *)(qb + o);
+    const double *g2 = A.meta + nb * DGW_META;
+    gn[u][0] = (real)g2[M_RHOINV];
+    gn[u][1] = (real)g2[M_LAM];
+    gn[u][2] = (real)g2[M_MU];
+    gn[u][3] = (real)g2[M_ZP];
+    gn[u][4] = (real)g2[M_ZS];
+  }
+  // the block's values to LDS
+#pragma unroll
+  for (int u = 0; u < QV; ++u) {
+    const int j = tid + u * kT;
+    if (j < sp.nv) {
+      const int o = sp.hd + SP::VW * j;
 #pragma unroll
       for (int l = 0; l < SP::VW; ++l) {
-        sw[o + l] = x[l] + b * y[l];
-        sq[o + l] = z[l];
+        sw[o + l] = vr[u][l] + b * vl[u][l];
+        sq[o + l] = vq[u][l];
       }
     }
-    const int o = sp.hd + SP::VW * sp.nv;
-    if (tid < sp.tl) {
-      sw[o + tid] = lrb[o + tid] + b * lqb[o + tid];
-      sq[o + tid] = qb[o + tid];
+  }
+  if (tid < sp.hd) {
+    sw[tid] = hr + b * hl;
+    sq[tid] = hq;
+  }
+  if (tid < sp.tl) {
+    sw[it] = tr_ + b * tl_;
+    sq[it] = tq;
+  }
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    const int j = tid + u * kT;
+    if (j < nE * DGW_META / 2) {
+      smeta[2 * j] = mm[u].x;
+      smeta[2 * j + 1] = mm[u].y;
     }
   }
-  for (int t = tid; t < nE * DGW_META; t += kT) smeta[t] = A.meta[k0 * DGW_META + t];
-  for (int t = tid; t < nE * 4; t += kT) scn[t] = A.conn[k0 * 4 + t];
   __syncthreads();
 
   // ---- faces: flux transpose and face gradient terms ------------------
-  for (int t = tid; t < nE * NF; t += kT) {
-    const int e = t / NF, fm = t - e * NF, f = fm / Nfp, m = fm - f * Nfp;
-    const int64_t k = k0 + e;
+#pragma unroll
+  for (int u = 0; u < FI; ++u) {
+    const int t = tid + u * kT;
+    if (t >= nE * NF) continue;
+    const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
     const double *g = smeta + e * DGW_META;
     const real *qe = sq + e * 9 * Np;
-    const int n1 = A.fmask[fm];
-    real qm[9], qp[9], z[9];
+    const int n1 = n1v[u];
+    const int cn = cnv[u];
+    real qm[9], qpp[9];
+    const real *z = zo[u];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      qm[c] = qe[c * Np + n1];
-      z[c] = zb[(k * 9 + c) * NF + fm];
-    }
-    const int cn = scn[e * 4 + f];
-    int64_t nb = -1;
-    int f2 = 0, m2 = 0;
+    for (int c = 0; c < 9; ++c) qm[c] = qe[c * Np + n1];
     if (cn >= 0) {
-      nb = cn >> 5;
-      f2 = (cn >> 3) & 3;
-      const int o = cn & 7;
-      const int tab = ((f * 4 + f2) * 6 + o) * Nfp + m;
-      const int n2 = A.nbtab[tab];
-      m2 = A.nbface[tab];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) qp[c] = q[(nb * 9 + c) * Np + n2];
+      for (int c = 0; c < 9; ++c) qpp[c] = qp[u][c];
     } else if (cn == CONN_FREE) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) qp[c] = qm[c];
+      for (int c = 0; c < 3; ++c) qpp[c] = qm[c];
 #pragma unroll
-      for (int c = 3; c < 9; ++c) qp[c] = -qm[c];
+      for (int c = 3; c < 9; ++c) qpp[c] = -qm[c];
     } else {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) qp[c] = 0;
+      for (int c = 0; c < 9; ++c) qpp[c] = 0;
     }
     real n[3] = {(real)g[M_NORMAL + 3 * f], (real)g[M_NORMAL + 3 * f + 1],
                  (real)g[M_NORMAL + 3 * f + 2]};
     real jv[3], js[6], jt[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) jv[a] = qp[a] - qm[a];
+    for (int a = 0; a < 3; ++a) jv[a] = qpp[a] - qm[a];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) js[a] = qp[3 + a] - qm[3 + a];
+    for (int a = 0; a < 6; ++a) js[a] = qpp[3 + a] - qm[3 + a];
     jt[0] = js[0] * n[0] + js[5] * n[1] + js[4] * n[2];
     jt[1] = js[5] * n[0] + js[1] * n[1] + js[3] * n[2];
     jt[2] = js[4] * n[0] + js[3] * n[1] + js[2] * n[2];
@@ -298,16 +384,11 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
     } else {
       // the neighbour's flux on this face, seen from the neighbour: normal
       // -n, jumps -[v] and [t], its own material, this element as "+"
-      const double *gn = A.meta + nb * DGW_META;
-      real zn[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) zn[c] = zb[(nb * 9 + c) * NF + f2 * Nfp + m2];
       real nn[3] = {-n[0], -n[1], -n[2]};
       real jvn[3] = {-jv[0], -jv[1], -jv[2]};
       real Jv2[3], Jt2[3], dv2[3], dt2[3], a1, a2, a3, a4;
-      flux_adjoint<real>(nn, jvn, jt, (real)gn[M_RHOINV], (real)gn[M_LAM],
-                         (real)gn[M_MU], (real)gn[M_ZP], (real)gn[M_ZS], zp, zs,
-                         izp, izs, zn, Jv2, Jt2, a1, a2, a3, a4, dv2, dt2);
+      flux_adjoint<real>(nn, jvn, jt, gn[u][0], gn[u][1], gn[u][2], gn[u][3], gn[u][4],
+                         zp, zs, izp, izs, zn[u], Jv2, Jt2, a1, a2, a3, a4, dv2, dt2);
       // this element is the neighbour's "+" side: [v]' = v_k - v_nb etc.
       out[0] += Jv2[0];
       out[1] += Jv2[1];

@@ -491,12 +491,15 @@ int dgw_set_mesh(dgw_ctx *c, int64_t nvert, const double *vxyz, int64_t K,
   c->d_conn = (int32_t *)c->dalloc(sizeof(int32_t) * c->mesh.conn.size());
   c->d_nbtab = (int32_t *)c->dalloc(sizeof(int32_t) * c->mesh.nbtab.size());
   c->d_nbnode = (uint8_t *)c->dalloc(c->mesh.nbnode.size());
-  if (!c->d_meta || !c->d_conn || !c->d_nbtab || !c->d_nbnode)
+  c->d_nbfnode = (uint8_t *)c->dalloc(c->mesh.nbfnode.size());
+  if (!c->d_meta || !c->d_conn || !c->d_nbtab || !c->d_nbnode || !c->d_nbfnode)
     return c->fail(DGW_ENOMEM, "device allocation failed (mesh)");
   if ((rc = c->upload(c->d_meta, c->mesh.geo.data(), sizeof(double) * c->mesh.geo.size()))) return rc;
   if ((rc = c->upload(c->d_conn, c->mesh.conn.data(), sizeof(int32_t) * c->mesh.conn.size()))) return rc;
   if ((rc = c->upload(c->d_nbtab, c->mesh.nbtab.data(), sizeof(int32_t) * c->mesh.nbtab.size()))) return rc;
   if ((rc = c->upload(c->d_nbnode, c->mesh.nbnode.data(), c->mesh.nbnode.size()))) return rc;
+  if ((rc = c->upload(c->d_nbfnode, c->mesh.nbfnode.data(), c->mesh.nbfnode.size())))
+    return rc;
   if ((rc = c->upload_operators())) return rc;
   if ((rc = c->alloc_shots())) return rc;
   c->have_mesh = true;

@@ -40,7 +40,7 @@ struct dgw_ctx {
   // device data
   double *d_meta = nullptr;
   int32_t *d_conn = nullptr, *d_nbtab = nullptr, *d_fmask = nullptr;
-  uint8_t *d_nbnode = nullptr;
+  uint8_t *d_nbnode = nullptr, *d_nbfnode = nullptr;
   void *d_DrT = nullptr, *d_DsT = nullptr, *d_DtT = nullptr, *d_LIFTT = nullptr;
   void *d_Avol = nullptr, *d_Alift = nullptr;   // MFMA operator fragments
   double *d_M = nullptr;

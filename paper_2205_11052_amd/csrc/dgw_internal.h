@@ -52,6 +52,7 @@ struct MeshData {
   std::vector<int32_t> nbtab;    // [4][4][6][Nfp] neighbour volume node
   std::vector<int32_t> nbface;   // [4][4][6][Nfp] neighbour face-local node
   std::vector<uint8_t> nbnode;   // [K][4][Nfp] neighbour volume node (interior faces)
+  std::vector<uint8_t> nbfnode;  // [K][4][Nfp] neighbour face node f2 Nfp + m2
   std::vector<double> volume;    // [K]
   std::vector<double> area;      // [K][4]
 };
@@ -132,7 +133,8 @@ struct AdjArgs {
   double *grad;                 // [S][K][3] (rho, lambda, mu)
   const double *meta;
   const int32_t *conn;
-  const int32_t *nbtab, *nbface;
+  const uint8_t *nbnode;        // [K][4 Nfp] neighbour volume node per face node
+  const uint8_t *nbfnode;       // [K][4 Nfp] neighbour face node f2 Nfp + m2
   const real *DrT, *DsT, *DtT;  // [j][i] = D(i, j)
   const real *Dr, *Ds, *Dt;     // [j][i] = D(j, i)
   const real *LIFT;             // [Np][4 Nfp]

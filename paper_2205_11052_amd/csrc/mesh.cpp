@@ -177,16 +177,21 @@ std::string build_mesh(const RefElem &R, int64_t nvert, const double *vxyz,
             if (R.fmask[f2 * Nfp + q] == idx)
               m.nbface[((f * 4 + f2) * 6 + o) * Nfp + mm] = q;
         }
-  // the same lookup resolved per element face node (Np <= 84 fits a byte)
+  // the same lookups resolved per element face node: the neighbour's
+  // volume node (Np <= 84 fits a byte) and its face node f2 Nfp + m2
+  // (4 Nfp <= 112 fits a byte)
   m.nbnode.assign((size_t)K * 4 * Nfp, 0);
+  m.nbfnode.assign((size_t)K * 4 * Nfp, 0);
   for (int64_t k = 0; k < K; ++k)
     for (int f = 0; f < 4; ++f) {
       const int32_t cn = m.conn[4 * k + f];
       if (cn < 0) continue;
       const int f2 = (cn >> 3) & 3, o = cn & 7;
-      for (int mm = 0; mm < Nfp; ++mm)
-        m.nbnode[(size_t)(4 * k + f) * Nfp + mm] =
-            (uint8_t)m.nbtab[((f * 4 + f2) * 6 + o) * Nfp + mm];
+      for (int mm = 0; mm < Nfp; ++mm) {
+        const int tab = ((f * 4 + f2) * 6 + o) * Nfp + mm;
+        m.nbnode[(size_t)(4 * k + f) * Nfp + mm] = (uint8_t)m.nbtab[tab];
+        m.nbfnode[(size_t)(4 * k + f) * Nfp + mm] = (uint8_t)(f2 * Nfp + m.nbface[tab]);
+      }
     }
   return "";
 }

@@ -5,7 +5,9 @@ libdgw.so; this module converts arrays, checks status codes and wires the
 PyTorch allocator and current stream into the library.
 """
 
+import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 
@@ -102,6 +104,20 @@ def permute_mesh(mesh, perm):
     return out
 
 
+# contexts still open at interpreter exit are destroyed by an exit hook,
+# while torch (whose allocator holds their device memory) is still alive
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_solvers():
+    for s in list(_LIVE):
+        try:
+            s.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """One dgw context: a mesh, a medium and ``nshots`` shots."""
 
@@ -120,6 +136,7 @@ class Solver:
         if rc:
             raise DGWError(rc, "dgw_create(order=%s, precision=%s, nshots=%s)"
                            % (order, precision, nshots))
+        _LIVE.add(self)
         if torch_allocator is None:
             torch_allocator = torch is not None and torch.cuda.is_available()
         self._callbacks = None
@@ -139,12 +156,15 @@ class Solver:
     def _use_torch_allocator(self):
         dev = torch.cuda.current_device()
 
+        cuda_alloc = torch.cuda.caching_allocator_alloc
+        cuda_free = torch.cuda.caching_allocator_delete
+        stream_of = torch.cuda.current_stream
+
         def alloc(nbytes, user):
-            return torch.cuda.caching_allocator_alloc(
-                int(nbytes), dev, torch.cuda.current_stream(dev))
+            return cuda_alloc(int(nbytes), dev, stream_of(dev))
 
         def free(ptr, user):
-            torch.cuda.caching_allocator_delete(ptr)
+            cuda_free(ptr)
 
         self._callbacks = (_lib.ALLOC_FN(alloc), _lib.FREE_FN(free))
         self._check(self.lib.dgw_set_allocator(self._ctx, self._callbacks[0],
