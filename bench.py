@@ -53,9 +53,9 @@ META_BYTES = 48 * 8 + 4 * 4        # per-element data + packed connectivity
 # is reported only while the kernel source hashes to the value it was
 # measured for and the same launch shape runs; otherwise traffic is null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "e2177220f81d640b17b4bc7d134356328db0333827f3d4232e8f734f093a8670",
+    "kernel_source_sha256": "635b93d472885b7211b27c011850b37751d444c51560591b76d40689563433dd",
     "launch_shape": (1, 7, 0),
-    "bytes_per_launch": 965221338,
+    "bytes_per_launch": 965143231,
 }
 
 
