@@ -230,6 +230,15 @@ int dgw_autotune(dgw_ctx *ctx, const char *cache_path, int *kernel,
  * dgw_adjoint return DGW_ESTATE unless tau = 1. */
 int dgw_set_flux(dgw_ctx *ctx, double tau);
 
+/* Absorbing sponge layer: per-element damping rate sigma [K] (finite,
+ * >= 0; NULL removes it).  The right-hand side of element k gains
+ * -sigma_k q on all nine fields (the damping layer of Cerjan, Kosloff,
+ * Kosloff and Reshef, Geophysics 50, 1985), so the energy falls by
+ * 2 sum_k sigma_k E_k per unit time on top of the flux's own dissipation;
+ * dgw_adjoint includes it exactly.  Requires the mesh (DGW_ESTATE);
+ * DGW_EINVAL for negative or non-finite rates. */
+int dgw_set_damping(dgw_ctx *ctx, const double *sigma);
+
 /* Launch shape of the stage kernel.  kernel 0: one thread per (element,
  * node) with the block's fields and lifted fluxes staged in LDS; then
  * elems_per_block is the elements per work-group (0 = default; DGW_EINVAL for

@@ -29,6 +29,10 @@ Semi-discrete strong form (nodal DG; Hesthaven and Warburton 2008):
       sigma_t += Fscale_f LIFT_f [lambda- (n.dv) I + mu- (dv n^T + n dv^T)].
 * boundary ghost states (Z+ = Z-): free surface v+ = v-, sigma+ = -sigma-
   (so t* = 0); absorbing v+ = 0, sigma+ = 0.
+* absorbing sponge layer (P.sponge = sigma [K] >= 0, default none): the
+  right-hand side gains -sigma_k q on every field of element k, the
+  damping layer of Cerjan, Kosloff, Kosloff and Reshef (Geophysics 50,
+  1985); the energy then changes by -2 sum_k sigma_k E_k.
 * fluid elements (mu = 0, acoustic; row f3): Zs = 0, so the tangential
   states above are well defined whenever one side is solid (the solid's
   tangential traction acts on a slip interface); where both sides are fluid
@@ -128,6 +132,8 @@ class Problem:
         # weight of the exact Riemann (upwind) flux; 1 - flux_tau goes to the
         # central flux
         self.flux_tau = 1.0
+        # per-element damping rate of the absorbing sponge layer (None: none)
+        self.sponge = None
 
     # --- sources and receivers -------------------------------------------
     def set_source(self, xyz, f0, t0, amp=1.0, moment=(1, 1, 1, 0, 0, 0)):
@@ -253,6 +259,8 @@ def rhs(P, q, rho, lam, mu):
     ], dim=1)                                                      # [K,9,4,Nfp]
     flux = flux * P.Fscale.to(dt_)[:, None, :, None]
     out = out + flux.reshape(K, 9, 4 * Nfp) @ P.LIFT.to(dt_).T
+    if P.sponge is not None:
+        out = out - P.sponge.to(dt_)[:, None, None] * q
     return out
 
 

@@ -100,6 +100,7 @@ void fill_adj(dgw_ctx *c, AdjArgs<real> &a, const void *q, void *lq, void *lr,
   a.LIFT = (const real *)c->adj->d_LIFT;
   a.fmask = c->d_fmask;
   a.facepos = c->adj->d_facepos;
+  a.sponge = c->have_sponge ? c->d_sponge : nullptr;
   a.K = c->mesh.K;
   a.shot_stride = c->mesh.K * 9 * c->R.Np;
   a.shot_step = c->adj->d_aux;

@@ -483,6 +483,12 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
       adj[6] = ri * (DTw(1, 2) + DTw(2, 1));
       adj[7] = ri * (DTw(0, 2) + DTw(2, 0));
       adj[8] = ri * (DTw(0, 1) + DTw(1, 0));
+      // the sponge's -sigma q is its own transpose
+      if (A.sponge) {
+        const real sg = (real)A.sponge[k];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) adj[c] -= sg * we[c * Np + i];
+      }
       const real *fa = sfa + e * 9 * NF;
 #pragma unroll
       for (int f = 0; f < 4; ++f) {

@@ -831,6 +831,29 @@ int dgw_set_launch(dgw_ctx *c, int kernel, int elems_per_block, int wgs_per_cu) 
   return DGW_OK;
 }
 
+int dgw_set_damping(dgw_ctx *c, const double *sigma) {
+  if (!c) return DGW_EINVAL;
+  if (!c->have_mesh) return c->fail(DGW_ESTATE, "set the mesh first");
+  c->invalidate_graph();
+  if (!sigma) {
+    c->have_sponge = false;
+    return DGW_OK;
+  }
+  const int64_t K = c->mesh.K;
+  for (int64_t k = 0; k < K; ++k)
+    if (!std::isfinite(sigma[k]) || sigma[k] < 0)
+      return c->fail(DGW_EINVAL, "damping rate negative or not finite at element " +
+                                     std::to_string(k));
+  if (!c->d_sponge) {
+    c->d_sponge = (double *)c->dalloc(sizeof(double) * K);
+    if (!c->d_sponge) return c->fail(DGW_ENOMEM, "device allocation failed (damping)");
+  }
+  int rc = c->upload(c->d_sponge, sigma, sizeof(double) * K);
+  if (rc) return rc;
+  c->have_sponge = true;
+  return DGW_OK;
+}
+
 int dgw_set_flux(dgw_ctx *c, double tau) {
   if (!c) return DGW_EINVAL;
   if (!(tau >= 0.0 && tau <= 1.0))

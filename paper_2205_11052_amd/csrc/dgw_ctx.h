@@ -35,6 +35,8 @@ struct dgw_ctx {
   bool have_mesh = false, have_mat = false, have_dt = false;
   double dt = 0;
   double flux_tau = 1.0;            // upwind weight of the face flux
+  double *d_sponge = nullptr;       // [K] damping rate (sponge layer)
+  bool have_sponge = false;
   std::vector<double> rho, lam, mu;
 
   // device data
@@ -128,6 +130,7 @@ inline void stage_args(const dgw_ctx *c, dgw::StageArgs<real> &a, const void *in
   a.src_vec = c->d_src_vec;
   a.src_par = c->d_src_par;
   a.ftau = (real)c->flux_tau;
+  a.sponge = c->have_sponge ? c->d_sponge : nullptr;
   a.rk_a = dgw::rk_a()[stage];
   a.rk_b = dgw::rk_b()[stage];
   a.rk_c = dgw::rk_c()[stage];

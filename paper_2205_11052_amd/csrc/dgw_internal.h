@@ -89,6 +89,7 @@ struct StageArgs {
   const double *src_vec;        // [S][Np]
   const double *src_par;        // [S][10]: moment[6], f0, t0, amp, unused
   real ftau;                    // weight of the upwind flux (1 - ftau: central)
+  const double *sponge;         // [K] damping rate, or null
   double rk_a, rk_b, rk_c, dt;
 };
 
@@ -140,6 +141,7 @@ struct AdjArgs {
   const real *LIFT;             // [Np][4 Nfp]
   const int32_t *fmask;         // [4 Nfp]
   const int32_t *facepos;       // [4][Np]: face-local index or -1
+  const double *sponge;         // [K] damping rate, or null
   int64_t K;
   int64_t shot_stride;
   const int64_t *shot_step;

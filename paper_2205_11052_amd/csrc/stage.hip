@@ -107,7 +107,8 @@ struct Mma<double> {
 // stores run over the block's contiguous span, fully coalesced.
 template <int N, typename real, int BE>
 __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real *sq,
-                                            real *sfl, const double *smeta, int nE,
+                                            real *sfl, const double *smeta,
+                                            const double *ssig, int nE,
                                             int64_t k0, int shot, int64_t step,
                                             real *qout, real *res, int oz, int tid) {
   using M = Mma<real>;
@@ -236,6 +237,7 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
     real rhs = sfl[t];
     const int e = t / (9 * Np), ci = t - e * 9 * Np, c = ci / Np, i = ci - c * Np;
     if (e == es && c >= 3) rhs += (real)(s * spar[c - 3] * A.src_vec[shot * Np + i]);
+    if (A.sponge) rhs -= (real)ssig[e] * sq[t];
     const real rn = first ? rdt * rhs : ra * rold + rdt * rhs;
     return {rn, sq[t] + rb * rn};
   };
@@ -270,7 +272,8 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
 template <int N, typename real, int BE>
 __device__ __forceinline__ void phase3_nodes(const StageArgs<real> &A, const real *sq,
                                              const real *sfl, const double *smeta,
-                                             int nE, int64_t k0, int shot, int64_t step,
+                                             const double *ssig, int nE, int64_t k0,
+                                             int shot, int64_t step,
                                              real *qout, real *res, int oz, int tid) {
   constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Sz<N>::Nfp;
   constexpr int UJ = Np % 7 == 0 ? 7 : Np % 5 == 0 ? 5 : 4;  // divides Np
@@ -359,6 +362,11 @@ __device__ __forceinline__ void phase3_nodes(const StageArgs<real> &A, const rea
     rhs[0] += V0;
     rhs[1] += V1;
     rhs[2] += V2;
+    if (A.sponge) {
+      const real sg = (real)ssig[e];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) rhs[c] -= sg * qe[c * Np + i];
+    }
     if (A.src_elem[shot] == k) {
       const double *sp = A.src_par + 10 * shot;
       const double s = ricker_d(((double)step + A.rk_c) * A.dt, sp[6], sp[7], sp[8]);
@@ -427,6 +435,7 @@ struct BlockLoad {
   typename SP::vec q[QV];
   real qh, qt;
   double2 m[MV];
+  double sg;   // damping rate of element tid of the block (threads < BE)
 };
 
 template <int N, typename real, int BE>
@@ -462,6 +471,11 @@ __device__ __forceinline__ void block_loads(const StageArgs<real> &A, int64_t it
     const int j = tid + u * kThreads;
     B.m[u] = mv[j < nE * DGW_META / 2 ? j : 0];
   }
+  // the sponge rate: read unconditionally (from the per-element data when
+  // there is no sponge, then discarded)
+  const double *sgp = A.sponge ? A.sponge : A.meta;
+  const double sgv = sgp[(ok ? k0 : 0) + (tid < nE ? tid : 0)];
+  B.sg = A.sponge ? sgv : 0.0;
 }
 
 template <int N, typename real, int BE, int V>
@@ -474,6 +488,7 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
   __shared__ real sq[BE * 9 * Np];
   __shared__ __attribute__((aligned(16))) real sfl[BE * NF * (V == 0 ? 6 : 9)];
   __shared__ double smeta[BE * DGW_META];
+  __shared__ double ssig[BE];
   const int shot = (int)(item / nblk);
   const int64_t step = A.shot_step[shot];
   if (step >= A.shot_len[shot]) return;            // uniform per work-group
@@ -528,6 +543,7 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
         smeta[2 * j + 1] = B.m[u].y;
       }
     }
+    if (tid < nE) ssig[tid] = B.sg;
   }
   __syncthreads();
 
@@ -619,9 +635,10 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
 
 
   if constexpr (V == 1)
-    phase3_mfma<N, real, BE>(A, sq, sfl, smeta, nE, k0, shot, step, qout, res, oz, tid);
+    phase3_mfma<N, real, BE>(A, sq, sfl, smeta, ssig, nE, k0, shot, step, qout, res, oz, tid);
   else
-    phase3_nodes<N, real, BE>(A, sq, sfl, smeta, nE, k0, shot, step, qout, res, oz, tid);
+    phase3_nodes<N, real, BE>(A, sq, sfl, smeta, ssig, nE, k0, shot, step, qout, res, oz,
+                              tid);
 }
 
 // One work-group per item.

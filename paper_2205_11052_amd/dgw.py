@@ -311,6 +311,15 @@ class Solver:
         self._check(self.lib.dgw_set_launch(self._ctx, int(kernel), int(elems),
                                             int(wgs_per_cu)), "dgw_set_launch")
 
+    def set_damping(self, sigma=None):
+        """Per-element damping rate of the absorbing sponge layer (None
+        removes it)."""
+        if sigma is None:
+            self._check(self.lib.dgw_set_damping(self._ctx, None), "dgw_set_damping")
+            return
+        sg = _host64(sigma)
+        self._check(self.lib.dgw_set_damping(self._ctx, _dptr(sg)), "dgw_set_damping")
+
     def set_flux(self, tau=1.0):
         """Upwind weight of the face flux (1 upwind, 0 central)."""
         self._check(self.lib.dgw_set_flux(self._ctx, float(tau)), "dgw_set_flux")

@@ -1,0 +1,178 @@
+"""The absorbing sponge layer (dgw_set_damping: right-hand side -sigma_k q
+on element k) on the GPU against the oracle with the same rates: FP64
+relative L2 <= 1e-12, FP32 <= 1e-5, both kernel variants, with a moment
+source and receivers; the full-size 82944-element order-4 workload in the
+benchmark's launch shapes; batched shots; the discrete adjoint with the
+sponge against the oracle's reverse-mode gradient (<= 1e-10); removing the
+sponge restores the undamped run bit for bit; rates are range-checked.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import adjoint as OA
+from oracle import solver as O
+from paper_2205_11052_amd.dgw import DGWError
+from gpu_helpers import (gpu_solver, oracle_problem, oracle_run, rel_l2,
+                         random_fields, say)
+
+pytestmark = pytest.mark.gpu
+
+MOMENT = (1.0, -0.5, 0.25, 0.3, -0.2, 0.1)
+
+
+def _random_medium(K, seed):
+    rng = np.random.default_rng(seed)
+    cp = rng.uniform(1.5, 3.0, K)
+    cs = cp / rng.uniform(1.5, 2.2, K)
+    rho = rng.uniform(1.0, 3.0, K)
+    return W.lame_from_velocities(cp, cs, rho)
+
+
+def _unit_sponge(mesh, sigma_max=6.0):
+    return W.sponge_profile(W.element_centroids(mesh), hi=(1.0, 1.0, 1.0),
+                            width=0.4, sigma_max=sigma_max)
+
+
+@pytest.mark.parametrize("N,kernel,prec,tau", [
+    (3, 0, 64, 1.0), (3, 1, 64, 1.0), (4, 0, 64, 1.0), (4, 1, 64, 1.0),
+    (4, 1, 64, 0.5), (4, 0, 32, 1.0), (4, 1, 32, 1.0)])
+def test_sponge_matches_oracle(N, kernel, prec, tau):
+    mesh = W.kuhn_cube(2, 1.0)
+    K = mesh["etov"].shape[0]
+    sig = _unit_sponge(mesh)
+    say("case sponge N=%d kernel=%d fp%d tau=%.1f K=%d damped=%d"
+        % (N, kernel, prec, tau, K, (sig > 0).sum()))
+    assert 0 < (sig > 0).sum() < K
+    rho, lam, mu = _random_medium(K, 80 + N)
+    P = oracle_problem(mesh, N)
+    P.flux_tau = tau
+    P.sponge = torch.as_tensor(sig)
+    dt = P.suggest_dt(rho, lam, mu, 0.5)
+    q0 = random_fields(K, P.Np, 90 + N)
+    src = np.array([0.37, 0.52, 0.61])
+    rec = np.array([[0.2, 0.3, 1.0], [0.8, 0.6, 0.5]])
+    P.set_source(src, 3.0, 0.1, 2.0, moment=MOMENT)
+    P.set_receivers(rec)
+    s = gpu_solver(mesh, N, rho, lam, mu, dt, precision=prec, kernel=kernel)
+    s.set_flux(tau)
+    s.set_damping(sig)
+    s.set_source(0, src, 3.0, 0.1, 2.0, moment=MOMENT)
+    s.set_receivers(0, rec, 16)
+    s.set_fields(0, q0)
+    nst = 7
+    s.step(nst)
+    q_ora, tr_ora = oracle_run(P, q0, rho, lam, mu, dt, nst, record=True)
+    err = rel_l2(s.get_fields(0), q_ora)
+    terr = rel_l2(s.read_traces(0), tr_ora)
+    say("sponge fields %.3e traces %.3e" % (err, terr))
+    tol = 1e-12 if prec == 64 else 1e-5
+    assert err <= tol and terr <= tol
+    if prec == 64:
+        # the damping is visible: the undamped oracle run differs
+        P.sponge = None
+        q_und, _ = oracle_run(P, q0, rho, lam, mu, dt, nst)
+        assert rel_l2(q_und, q_ora) > 1e3 * tol
+
+
+def test_full_size_sponge_fp64():
+    """The 82944-element order-4 layered workload with a sponge one unit
+    thick on the five absorbing sides, random fields, two steps against the
+    oracle in the benchmark's launch shapes, then a batch of two shots."""
+    w = W.build_workload("c1_layered_n24")
+    cen = W.element_centroids(w["mesh"])
+    sig = W.sponge_profile(cen, width=1.0, sigma_max=3.0)
+    say("case full sponge K=%d damped=%d" % (w["K"], (sig > 0).sum()))
+    P = oracle_problem(w["mesh"], w["N"])
+    P.sponge = torch.as_tensor(sig)
+    rho, lam, mu = w["rho"], w["lam"], w["mu"]
+    dt = P.suggest_dt(rho, lam, mu, w["cfl"])
+    q0 = random_fields(w["K"], P.Np, 14)
+    P.set_source(w["source"], w["f0"], 0.05, w["amp"])
+    P.set_receivers(w["receivers"])
+    q_ora, tr_ora = oracle_run(P, q0, rho, lam, mu, dt, 2, record=True)
+    s = gpu_solver(w["mesh"], w["N"], rho, lam, mu, dt, nshots=2)
+    s.set_damping(sig)
+    for i in range(2):
+        s.set_source(i, w["source"], w["f0"], 0.05, w["amp"])
+        s.set_receivers(i, w["receivers"], 8)
+    for shape in ((1, 7, 0), (0, 7, 0), (1, 3, 0), (1, 7, 3)):
+        s.set_launch(*shape)
+        for i in range(2):
+            s.set_fields(i, q0)
+        s.step(2)
+        for i in range(2):
+            err = rel_l2(s.get_fields(i), q_ora)
+            terr = rel_l2(s.read_traces(i), tr_ora)
+            say("full sponge shape %s shot %d fields %.3e traces %.3e"
+                % (shape, i, err, terr))
+            assert err <= 1e-12 and terr <= 1e-12
+
+
+def test_removing_the_sponge_restores_the_undamped_run():
+    mesh = W.kuhn_cube(2, 1.0)
+    K = mesh["etov"].shape[0]
+    rho, lam, mu = _random_medium(K, 7)
+    q0 = random_fields(K, 35, 8)
+    out = []
+    for damp in (False, True):
+        s = gpu_solver(mesh, 4, rho, lam, mu, 1e-3, kernel=1)
+        if damp:
+            s.set_damping(_unit_sponge(mesh))
+            s.set_fields(0, q0)
+            s.step(3)
+            s.set_damping(None)
+        s.set_fields(0, q0)
+        s.step(5)
+        out.append(s.get_fields(0))
+        s.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def test_damping_rates_checked():
+    mesh = W.kuhn_cube(2, 1.0)
+    K = mesh["etov"].shape[0]
+    rho, lam, mu = _random_medium(K, 1)
+    s = gpu_solver(mesh, 2, rho, lam, mu, 1e-3)
+    for bad in (-1e-3, np.nan, np.inf):
+        sig = np.zeros(K)
+        sig[K // 2] = bad
+        with pytest.raises(DGWError) as e:
+            s.set_damping(sig)
+        assert e.value.code == -1
+
+
+def test_adjoint_with_sponge_equals_oracle():
+    mesh = W.kuhn_cube(2, 1.0)
+    K = mesh["etov"].shape[0]
+    true = _random_medium(K, 50)
+    start = [m * (1 + 0.05 * np.sin(np.arange(K) + i)) for i, m in enumerate(true)]
+    sig = _unit_sponge(mesh)
+    N, nsteps = 3, 24
+    P = oracle_problem(mesh, N)
+    P.sponge = torch.as_tensor(sig)
+    dt = P.suggest_dt(*true, 0.5)
+    src, f0, t0 = np.array([0.41, 0.47, 0.53]), 4.0, 0.05
+    rec = np.array([[0.2, 0.3, 1.0], [0.8, 0.6, 0.7], [0.1, 0.9, 0.0]])
+    P.set_source(src, f0, t0)
+    P.set_receivers(rec)
+    t = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64))
+    q0 = torch.zeros(K, 9, P.Np, dtype=torch.float64)
+    with torch.no_grad():
+        _, d_obs = O.run(P, q0, *(t(a) for a in true), dt, nsteps, record=True)
+    say("case adjoint with sponge K=%d" % K)
+    J_o, gr, gl, gm = OA.misfit_gradient(P, *(t(a) for a in start), q0, dt, nsteps,
+                                         d_obs, ckpt_every=7)
+    s = gpu_solver(mesh, N, *start, dt)
+    s.set_damping(sig)
+    s.set_source(0, src, f0, t0)
+    s.set_receivers(0, rec, nsteps)
+    s.zero_fields()
+    mis = s.forward_checkpointed(nsteps, 7, d_obs.numpy()[None])
+    g = s.adjoint()
+    assert abs(mis[0] - J_o.item()) <= 1e-12 * J_o.item()
+    errs = [rel_l2(g[i][0], ref.numpy()) for i, ref in enumerate((gr, gl, gm))]
+    say("sponge adjoint misfit %.6e grad rel err %.2e %.2e %.2e" % (mis[0], *errs))
+    assert max(errs) <= 1e-10

@@ -77,3 +77,19 @@ def blob_start_medium(centroids, centre=(5.0, 5.0, 8.5), width=1.0,
     cp = cp * (1.0 - depth * np.exp(-d2 / (2.0 * width * width)))
     r, lam, mu = lame_from_velocities(cp, cp / np.sqrt(3.0), rho)
     return r, lam, mu, cp
+
+
+def sponge_profile(centroids, lo=(0.0, 0.0, 0.0), hi=(BOX, BOX, BOX), width=1.0,
+                   sigma_max=1.0, faces=("x-", "x+", "y-", "y+", "z-")):
+    """Per-element damping rate of an absorbing sponge layer inside the box
+    [lo, hi]: sigma = sigma_max (1 - d / width)^2 where d < width is the
+    centroid's distance to the nearest listed face ("x-" is x = lo[0], "z+"
+    is z = hi[2], ...), 0 elsewhere.  The default lists every face but the
+    top (free surface)."""
+    c = np.asarray(centroids, dtype=np.float64)
+    d = np.full(c.shape[0], np.inf)
+    for f in faces:
+        a = "xyz".index(f[0])
+        d = np.minimum(d, c[:, a] - lo[a] if f[1] == "-" else hi[a] - c[:, a])
+    s = np.clip(1.0 - d / width, 0.0, None)
+    return sigma_max * s * s
