@@ -37,6 +37,22 @@ Semi-discrete strong form (nodal DG; Hesthaven and Warburton 2008):
   states above are well defined whenever one side is solid (the solid's
   tangential traction acts on a slip interface); where both sides are fluid
   (Zs- + Zs+ = 0) there is no tangential coupling: t*_T = t-_T, v*_T = v-_T.
+* anisotropic elements (P.stiffness = C [K, 6, 6], default none; row f3):
+  the stiffness in Voigt order (xx, yy, zz, yz, xz, xy) with engineering
+  shear strains, symmetric positive definite, replaces lambda and mu
+  (rho stays).  Volume: sigma_t = C e(v) with
+  e = (dx vx, dy vy, dz vz, dy vz + dz vy, dx vz + dz vx, dx vy + dy vx).
+  Faces: the strain of sym(a n^T) is N(n) a, with the 6x3 matrix
+  N(n) = [[nx,0,0],[0,ny,0],[0,0,nz],[0,nz,ny],[nz,0,nx],[ny,nx,0]]; the
+  traction is t = N(n)^T sigma, and along the normal coordinate x_n the
+  pair (t, v) obeys rho v_t = d t / d x_n, t_t = G d v / d x_n with the
+  Christoffel matrix G = N^T C N (3x3, SPD).  Its characteristic variables t -+ Z v, with the
+  impedance matrix Z = (rho G)^(1/2) (the SPD square root), travel away
+  from the face on either side, so the exact Riemann states are
+      v* = (Z- + Z+)^-1 (Z- v- + Z+ v+ + t+ - t-),   t* = t- + Z- (v* - v-)
+  (for isotropic C, Z = Zp n n^T + Zs (I - n n^T) and these are the states
+  above).  Stress flux: Fscale LIFT C N(n) dv.  Boundary ghost states as
+  above with Z+ = Z-.  Energy: the potential term is sigma^T C^-1 sigma.
 * flux variant (P.flux_tau = tau in [0, 1], default 1): the states used are
   tau (t*, v*) + (1 - tau) ((t- + t+)/2, (v- + v+)/2), i.e. a convex
   combination of the upwind flux and the central flux (the alpha-flux family
@@ -134,6 +150,9 @@ class Problem:
         self.flux_tau = 1.0
         # per-element damping rate of the absorbing sponge layer (None: none)
         self.sponge = None
+        # per-element Voigt stiffness [K, 6, 6] of anisotropic elements
+        # (None: isotropic lambda, mu)
+        self.stiffness = None
 
     # --- sources and receivers -------------------------------------------
     def set_source(self, xyz, f0, t0, amp=1.0, moment=(1, 1, 1, 0, 0, 0)):
@@ -159,8 +178,28 @@ class Problem:
         return setup.suggest_dt(self.geo, rho, lam, mu, self.N, cfl)
 
 
+def voigt_nmat(n):
+    """N(n) for normals n [..., 3]: the 6x3 matrix mapping a vector a to the
+    Voigt strain (engineering shears) of sym(a n^T); its transpose maps a
+    Voigt stress to the traction sigma n.  Returns [..., 6, 3]."""
+    nx, ny, nz = n[..., 0], n[..., 1], n[..., 2]
+    z = torch.zeros_like(nx)
+    rows = [[nx, z, z], [z, ny, z], [z, z, nz], [z, nz, ny], [nz, z, nx],
+            [ny, nx, z]]
+    return torch.stack([torch.stack(r, dim=-1) for r in rows], dim=-2)
+
+
+def impedance(rho, C, Nm):
+    """Z = (rho N^T C N)^(1/2), the SPD square root by eigendecomposition;
+    rho [...], C [..., 6, 6], Nm [..., 6, 3] -> [..., 3, 3]."""
+    G = Nm.transpose(-1, -2) @ C @ Nm * rho[..., None, None]
+    w, V = torch.linalg.eigh(G)
+    return V @ torch.diag_embed(torch.sqrt(w)) @ V.transpose(-1, -2)
+
+
 def rhs(P, q, rho, lam, mu):
-    """L q for q [K, 9, Np] (no source); rho, lam, mu are [K] tensors."""
+    """L q for q [K, 9, Np] (no source); rho, lam, mu are [K] tensors
+    (lam and mu unused where P.stiffness is set)."""
     dt_ = q.dtype
     Dr, Ds, Dt = P.Dr.to(dt_), P.Ds.to(dt_), P.Dt.to(dt_)
     Xinv = P.Xinv.to(dt_)
@@ -184,6 +223,12 @@ def rhs(P, q, rho, lam, mu):
         m * (dx(VX, 2) + dx(VZ, 0)),
         m * (dx(VX, 1) + dx(VY, 0)),
     ], dim=1)                                                      # [K,9,Np]
+    C = P.stiffness
+    if C is not None:
+        strain = torch.stack([dx(VX, 0), dx(VY, 1), dx(VZ, 2), dx(VY, 2) + dx(VZ, 1),
+                              dx(VX, 2) + dx(VZ, 0), dx(VX, 1) + dx(VY, 0)], dim=1)
+        out = torch.cat([out[:, 0:3],
+                         torch.einsum("kij,kjn->kin", C.to(dt_), strain)], dim=1)
 
     # ---- faces --------------------------------------------------------
     K, Nfp = P.K, P.Nfp
@@ -236,12 +281,26 @@ def rhs(P, q, rho, lam, mu):
                       tmT)
     vsn = (Zp_m * vmn + Zp_p * vpn + tpn - tmn) / (Zp_m + Zp_p)
     vsT = torch.where(solid, (Zs_m * vmT + Zs_p * vpT + tpT - tmT) / zs_den, vmT)
+    tstar, vstar = tsn * n + tsT, vsn * n + vsT
+    if C is not None:
+        # impedance matrices of both sides on each face, with the own
+        # outward normal (G(n) = G(-n)); the ghost side of a boundary face
+        # has the own one
+        Nm = voigt_nmat(P.normals)                                 # [K,4,6,3]
+        Zm = impedance(rho[:, None].expand(K, 4), C[:, None].expand(K, 4, 6, 6), Nm)
+        Zn = impedance(rho[nb], C[nb], Nm)
+        Zpl = torch.where(bnd[:, :, None, None], Zm, Zn)
+        Zm, Zpl = Zm.to(dt_), Zpl.to(dt_)
+        mv = lambda Z, x: torch.einsum("kfij,kjfn->kifn", Z, x)   # Z x per face
+        W = torch.linalg.inv(Zm + Zpl)
+        vstar = mv(W, mv(Zm, vm) + mv(Zpl, vp) + tp - tm)
+        tstar = tm + mv(Zm, vstar - vm)
     # flux states: tau times the exact Riemann states plus (1 - tau) times
     # the central (averaged) states; tau = 1 is the upwind flux, tau = 0
     # the central one (boundary ghost states as above in both)
     tau = P.flux_tau
-    tS = tau * (tsn * n + tsT) + (1.0 - tau) * 0.5 * (tm + tp)
-    vS = tau * (vsn * n + vsT) + (1.0 - tau) * 0.5 * (vm + vp)
+    tS = tau * tstar + (1.0 - tau) * 0.5 * (tm + tp)
+    vS = tau * vstar + (1.0 - tau) * 0.5 * (vm + vp)
     dT = tS - tm                                                   # [K,3,4,Nfp]
     dV = vS - vm
     ndv = (n * dV).sum(dim=1)                                      # [K,4,Nfp]
@@ -257,6 +316,11 @@ def rhs(P, q, rho, lam, mu):
         mm * (dV[:, 0] * n[:, 2] + dV[:, 2] * n[:, 0]),
         mm * (dV[:, 0] * n[:, 1] + dV[:, 1] * n[:, 0]),
     ], dim=1)                                                      # [K,9,4,Nfp]
+    if C is not None:
+        # stress flux C N(n) dv
+        eN = torch.einsum("kfij,kjfn->kifn", voigt_nmat(P.normals).to(dt_), dV)
+        flux = torch.cat([flux[:, 0:3], torch.einsum("kij,kjfn->kifn", C.to(dt_), eN)],
+                         dim=1)
     flux = flux * P.Fscale.to(dt_)[:, None, :, None]
     out = out + flux.reshape(K, 9, 4 * Nfp) @ P.LIFT.to(dt_).T
     if P.sponge is not None:
@@ -319,6 +383,10 @@ def energy(P, q, rho, lam, mu):
     elastic = (diag + 2.0 * off) / (2.0 * mus) \
         - lam / (2.0 * mus * (3.0 * lam + 2.0 * mus)) * trq
     pot = torch.where(fluid, trq / (9.0 * lam), elastic)
+    if P.stiffness is not None:
+        S = torch.linalg.inv(P.stiffness).to(q.dtype)             # compliance
+        sM = torch.einsum("kin,nm->kim", q[:, 3:9], M)
+        pot = torch.einsum("kij,kim,kjm->k", S, sM, q[:, 3:9])
     return 0.5 * torch.sum(P.J.to(q.dtype) * (rho * kin + pot))
 
 

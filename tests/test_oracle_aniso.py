@@ -1,0 +1,160 @@
+"""Pins of the anisotropic elements (P.stiffness: Voigt C per element; exact
+Riemann states from the impedance matrices Z = (rho N^T C N)^(1/2)).
+
+* An isotropic C reproduces the isotropic right-hand side and energy (whose
+  pins are independent of this code path) on heterogeneous media, for the
+  upwind and the blended flux, on boxed, periodic and general meshes: the
+  impedance-matrix Riemann states then equal the normal/tangential ones.
+* An affine velocity field on a fully anisotropic heterogeneous medium gets
+  the stress rate sum_kl C_ijkl dv_k/dx_l of the full stiffness tensor
+  (not the Voigt product the oracle computes), on interior elements.
+* Plane waves of a homogeneous fully anisotropic medium (the slowest
+  quasi-S and the quasi-P wave, from the Christoffel eigenproblem) converge
+  at order >= N + 1/2 (order 2, periodic meshes of 3^3 and 6^3 cubes).
+* On heterogeneous anisotropic media the symmetric part of M_E L (M_E the
+  energy matrix with the compliance C^-1) is negative semidefinite for the
+  upwind flux (and nonzero) and zero for the central flux, on periodic
+  meshes and on meshes with free-surface and absorbing faces.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import solver as O
+from oracle_helpers import assemble_L, random_medium, tensors
+
+
+def _t(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float64))
+
+
+@pytest.mark.parametrize("kind", ["boxed", "periodic", "general"])
+@pytest.mark.parametrize("tau", [1.0, 0.5])
+def test_isotropic_stiffness_reproduces_isotropic(kind, tau):
+    mesh = {"boxed": lambda: W.kuhn_cube(2, 1.0),
+            "periodic": lambda: W.kuhn_cube(3, 1.0, periodic=True),
+            "general": lambda: W.general_mesh(3, 1.0, seed=4)}[kind]()
+    P = O.Problem(mesh, 3)
+    P.flux_tau = tau
+    rho, lam, mu = tensors(*random_medium(P.K, 17))
+    q = _t(np.random.default_rng(18).standard_normal((P.K, 9, P.Np)))
+    r0 = O.rhs(P, q, rho, lam, mu)
+    e0 = O.energy(P, q, rho, lam, mu)
+    P.stiffness = _t(W.isotropic_stiffness(lam.numpy(), mu.numpy()))
+    # lambda and mu are not used where the stiffness is set
+    r1 = O.rhs(P, q, rho, lam * 0 + 1.0, mu * 0 + 1.0)
+    e1 = O.energy(P, q, rho, lam * 0 + 1.0, mu * 0 + 1.0)
+    assert float((r1 - r0).norm() / r0.norm()) <= 1e-13
+    assert abs(float(e1 - e0)) <= 1e-13 * float(e0)
+
+
+def _full_tensor(Cv):
+    pairs = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+    idx = np.zeros((3, 3), dtype=int)
+    for a, (i, j) in enumerate(pairs):
+        idx[i, j] = idx[j, i] = a
+    return Cv[..., idx[:, :, None, None], idx[None, None, :, :]]     # [...,3,3,3,3]
+
+
+def test_affine_velocity_stress_rate_is_the_tensor_contraction():
+    mesh = W.kuhn_cube(3, 1.0)
+    N = 2
+    P = O.Problem(mesh, N)
+    rho, C = W.random_stiffness(P.K, 5)
+    P.stiffness = _t(C)
+    rng = np.random.default_rng(6)
+    G = rng.standard_normal((3, 3))                   # dv_k / dx_l = G[k, l]
+    a = rng.standard_normal(3)
+    x = W.lattice_node_coords(mesh, N)                # [K, Np, 3]
+    q = np.zeros((P.K, 9, P.Np))
+    q[:, 0:3] = (a[None, None, :] + x @ G.T).transpose(0, 2, 1)
+    r = O.rhs(P, _t(q), _t(rho), _t(np.ones(P.K)), _t(np.ones(P.K))).numpy()
+    Ct = _full_tensor(C)                              # [K,3,3,3,3]
+    sig = np.einsum("kijab,ab->kij", Ct, G)           # sum_kl C_ijkl dv_k/dx_l
+    pairs = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+    want = np.stack([sig[:, i, j] for i, j in pairs], axis=1)      # [K,6]
+    inner = np.all(P.bc == 0, axis=1)
+    assert inner.sum() > 0
+    err = np.abs(r[inner, 3:9] - want[inner, :, None]).max()
+    assert err <= 1e-11 * np.abs(want).max()
+    assert np.abs(r[inner, 0:3]).max() <= 1e-11 * np.abs(want).max()
+
+
+def _aniso_plane_wave_error(N, n, mode, C, rho, T=0.1):
+    mesh = W.kuhn_cube(n, 1.0, periodic=True)
+    P = O.Problem(mesh, N)
+    P.stiffness = _t(np.broadcast_to(C, (P.K, 6, 6)).copy())
+    x = W.lattice_node_coords(mesh, N)
+    d = np.array([1.0, 0.0, 0.0])
+    kk = 2 * np.pi
+    st = lambda t: W.anisotropic_plane_wave_state(x, t, d, kk, rho, C,
+                                                  mode).transpose(0, 2, 1)
+    # time step from the fastest speed over 500 random directions
+    dirs = np.random.default_rng(0).standard_normal((500, 3))
+    Nm = O.voigt_nmat(_t(dirs / np.linalg.norm(dirs, axis=1)[:, None])).numpy()
+    cmax2 = np.linalg.eigvalsh(Nm.transpose(0, 2, 1) @ C @ Nm).max() / rho
+    ones = np.ones(P.K)
+    dt = P.suggest_dt(ones * rho, ones * (1.05 * cmax2 * rho), ones * 0.0, 0.5)
+    ns = int(math.ceil(T / dt))
+    r = _t(ones * rho)
+    q, _ = O.run(P, _t(st(0.0).copy()), r, r, r, T / ns, ns)
+    qe = st(T)
+    return np.linalg.norm(q.numpy() - qe) / np.linalg.norm(qe)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_anisotropic_plane_wave_converges(mode):
+    N, levels = 2, (3, 6)
+    rho, C = W.random_stiffness(1, 9, strength=0.8)
+    e = [_aniso_plane_wave_error(N, n, mode, C[0], float(rho[0])) for n in levels]
+    rate = math.log(e[0] / e[1]) / math.log(levels[1] / levels[0])
+    assert e[1] < 0.02
+    assert rate >= N + 0.5, (e, rate)
+
+
+def _energy_matrix_aniso(P, rho, C):
+    M = P.ops["M"]
+    blocks = []
+    for k in range(P.K):
+        W9 = np.zeros((9, 9))
+        W9[:3, :3] = rho[k] * np.eye(3)
+        W9[3:, 3:] = np.linalg.inv(C[k])
+        blocks.append(float(P.J[k]) * np.kron(W9, M))
+    n = P.K * 9 * P.Np
+    ME = np.zeros((n, n))
+    for k, b in enumerate(blocks):
+        s = k * 9 * P.Np
+        ME[s:s + 9 * P.Np, s:s + 9 * P.Np] = b
+    return ME
+
+
+@pytest.mark.parametrize("N,periodic", [(1, False), (2, False), (1, True)])
+def test_energy_matrix_upwind_dissipates_central_conserves(N, periodic):
+    m = W.kuhn_cube(3, 1.0, periodic=True) if periodic else W.kuhn_cube(2, 1.0)
+    P = O.Problem(m, N)
+    rho, C = W.random_stiffness(P.K, 30 + N)
+    P.stiffness = _t(C)
+    ME = _energy_matrix_aniso(P, rho, C)
+    r = _t(rho)
+    one = _t(np.ones(P.K))
+    # energy() agrees with the quadratic form
+    q = np.random.default_rng(3).standard_normal(P.K * 9 * P.Np)
+    e1 = O.energy(P, _t(q).view(P.K, 9, P.Np), r, one, one).item()
+    assert abs(e1 - 0.5 * q @ ME @ q) <= 1e-12 * e1
+    scale = None
+    for tau in (1.0, 0.0):
+        P.flux_tau = tau
+        S = ME @ assemble_L(P, r, one, one)
+        ev = np.linalg.eigvalsh(S + S.T)
+        if tau == 1.0:
+            scale = np.abs(ev).max()
+            assert ev.max() <= 1e-11 * scale, (periodic, ev.max() / scale)
+            assert ev.min() < -1e-3 * scale
+        else:
+            # the central flux exchanges no energy across interior faces,
+            # and none at free-surface or absorbing ghost states either
+            assert np.abs(ev).max() <= 1e-11 * scale, (periodic, np.abs(ev).max() / scale)

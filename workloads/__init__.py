@@ -13,16 +13,18 @@ input is reproducible.
 
 from .mesh import kuhn_cube, general_mesh, lattice_node_coords, element_centroids
 from .medium import (layered_medium, blob_start_medium, homogeneous_medium,
-                     lame_from_velocities, sponge_profile)
+                     lame_from_velocities, sponge_profile,
+                     isotropic_stiffness, random_stiffness, stiffness_upper)
 from .shots import (default_source, default_receivers, batched_shots,
                     ricker_f0)
-from .planewave import plane_wave_state
+from .planewave import plane_wave_state, anisotropic_plane_wave_state
 from .configs import CONFIGS, get_config, build_workload
 
 __all__ = [
     "kuhn_cube", "lattice_node_coords", "element_centroids",
     "layered_medium", "blob_start_medium", "homogeneous_medium",
-    "lame_from_velocities", "sponge_profile", "default_source", "default_receivers",
+    "lame_from_velocities", "sponge_profile", "isotropic_stiffness",
+    "random_stiffness", "stiffness_upper", "anisotropic_plane_wave_state", "default_source", "default_receivers",
     "batched_shots", "ricker_f0", "plane_wave_state", "CONFIGS",
     "get_config", "build_workload",
 ]

@@ -93,3 +93,39 @@ def sponge_profile(centroids, lo=(0.0, 0.0, 0.0), hi=(BOX, BOX, BOX), width=1.0,
         d = np.minimum(d, c[:, a] - lo[a] if f[1] == "-" else hi[a] - c[:, a])
     s = np.clip(1.0 - d / width, 0.0, None)
     return sigma_max * s * s
+
+
+def isotropic_stiffness(lam, mu):
+    """Voigt stiffness [K, 6, 6] (order xx, yy, zz, yz, xz, xy; engineering
+    shear strains) of isotropic elements."""
+    lam = np.atleast_1d(np.asarray(lam, dtype=np.float64))
+    mu = np.atleast_1d(np.asarray(mu, dtype=np.float64))
+    C = np.zeros(lam.shape + (6, 6))
+    C[:, :3, :3] = lam[:, None, None]
+    for i in range(3):
+        C[:, i, i] += 2.0 * mu
+        C[:, 3 + i, 3 + i] = mu
+    return C
+
+
+def random_stiffness(K, seed, strength=0.5):
+    """Seeded fully anisotropic stiffness [K, 6, 6]: a random isotropic
+    background (cp in [1.5, 3], cp/cs in [1.5, 2.2], rho in [1, 3]) plus
+    strength * mu * G G^T / 6 with G a 6x6 standard-normal matrix per
+    element (symmetric positive definite, every one of the 21 entries
+    nonzero).  Returns (rho, C)."""
+    rng = np.random.default_rng(seed)
+    cp = rng.uniform(1.5, 3.0, K)
+    cs = cp / rng.uniform(1.5, 2.2, K)
+    rho = rng.uniform(1.0, 3.0, K)
+    rho, lam, mu = lame_from_velocities(cp, cs, rho)
+    G = rng.standard_normal((K, 6, 6))
+    C = isotropic_stiffness(lam, mu) + strength * mu[:, None, None] * (G @ G.transpose(0, 2, 1)) / 6.0
+    return rho, C
+
+
+def stiffness_upper(C):
+    """The 21 upper-triangle entries of each Voigt stiffness, row by row
+    (C11 C12 ... C16 C22 ... C66): [K, 21]."""
+    iu = np.triu_indices(6)
+    return np.ascontiguousarray(np.asarray(C, dtype=np.float64)[:, iu[0], iu[1]])

@@ -44,3 +44,39 @@ def plane_wave_state(x, t, kind, direction, wavenumber, rho, lam, mu,
     out[..., 7] = S[0, 2] * f
     out[..., 8] = S[0, 1] * f
     return out
+
+
+def anisotropic_plane_wave_state(x, t, direction, wavenumber, rho, C, mode):
+    """Plane wave in a homogeneous anisotropic medium (Voigt stiffness C
+    [6, 6], order xx yy zz yz xz xy, engineering shears): with the
+    Christoffel matrix G(d)_ik = sum_jl C_ijkl d_j d_l, mode m (0, 1, 2 by
+    increasing speed) has G p = rho c^2 p, |p| = 1, and
+    v = p f(d.x - c t), sigma = -(1/c) C e(p, d) f(d.x - c t), where
+    e(p, d) is the Voigt strain of sym(p d^T).  Substituting into
+    rho v_t = div(sigma) and sigma_t = C e(grad v) gives back G p = rho c^2 p.
+    Returns [..., 9] at points x [..., 3]."""
+    d = np.asarray(direction, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    C = np.asarray(C, dtype=np.float64)
+    # full tensor from Voigt (index pairs 00 11 22 12 02 01)
+    pairs = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+    vi = {}
+    for a, (i, j) in enumerate(pairs):
+        vi[(i, j)] = vi[(j, i)] = a
+    Ct = np.empty((3, 3, 3, 3))
+    for i in range(3):
+        for j in range(3):
+            for k in range(3):
+                for l in range(3):
+                    Ct[i, j, k, l] = C[vi[(i, j)], vi[(k, l)]]
+    G = np.einsum("ijkl,j,l->ik", Ct, d, d)
+    w, V = np.linalg.eigh(G / rho)
+    c = np.sqrt(w[mode])
+    p = V[:, mode]
+    sig = -np.einsum("ijkl,k,l->ij", Ct, p, d) / c        # symmetric in i, j
+    f = np.sin(wavenumber * (np.asarray(x, dtype=np.float64) @ d - c * t))
+    out = np.empty(f.shape + (9,), dtype=np.float64)
+    out[..., 0:3] = f[..., None] * p
+    for a, (i, j) in enumerate(pairs):
+        out[..., 3 + a] = sig[i, j] * f
+    return out
