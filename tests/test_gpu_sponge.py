@@ -33,14 +33,14 @@ def _random_medium(K, seed):
 
 def _unit_sponge(mesh, sigma_max=6.0):
     return W.sponge_profile(W.element_centroids(mesh), hi=(1.0, 1.0, 1.0),
-                            width=0.4, sigma_max=sigma_max)
+                            width=0.3, sigma_max=sigma_max)
 
 
 @pytest.mark.parametrize("N,kernel,prec,tau", [
     (3, 0, 64, 1.0), (3, 1, 64, 1.0), (4, 0, 64, 1.0), (4, 1, 64, 1.0),
     (4, 1, 64, 0.5), (4, 0, 32, 1.0), (4, 1, 32, 1.0)])
 def test_sponge_matches_oracle(N, kernel, prec, tau):
-    mesh = W.kuhn_cube(2, 1.0)
+    mesh = W.kuhn_cube(3, 1.0)
     K = mesh["etov"].shape[0]
     sig = _unit_sponge(mesh)
     say("case sponge N=%d kernel=%d fp%d tau=%.1f K=%d damped=%d"
