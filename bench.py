@@ -45,6 +45,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 META_BYTES = 48 * 8 + 4 * 4        # per-element data + packed connectivity
+ANI_BYTES = 120 * 8                # anisotropic per-element data (DGW_ANI doubles)
 
 
 # HBM traffic of the order-4 FP64 stage kernel on this workload, measured
@@ -283,6 +284,48 @@ def general_mesh_form(torch, stream, w, steps, warmup, structured_ms):
     return out
 
 
+def variants_form(torch, stream, w, steps, warmup, plain_ms):
+    """Method variants on the workload's mesh (82944 elements, order 4,
+    FP64), each with the launch shape the autotuner picks for it: the
+    layered medium with an absorbing sponge one unit thick on the five
+    absorbing sides, and a fully anisotropic heterogeneous medium (seeded
+    random stiffness per element; node-per-thread form).  Algorithmic bytes
+    add the per-element anisotropic data (DGW_ANI doubles) read once."""
+    import workloads as W
+    K, Np = w["K"], 35
+    cen = W.element_centroids(w["mesh"])
+    out = {}
+    for name in ("sponge", "anisotropic"):
+        with torch.cuda.stream(stream):
+            from paper_2205_11052_amd import Solver
+            s = Solver(w["N"], 64, 1, stream=stream.cuda_stream)
+            s.set_mesh_dict(w["mesh"])
+            extra = 0
+            if name == "sponge":
+                s.set_material(w["rho"], w["lam"], w["mu"])
+                s.set_damping(W.sponge_profile(cen, width=1.0, sigma_max=3.0))
+            else:
+                rho, C = W.random_stiffness(K, 2205)
+                s.set_material(rho, np.ones(K), np.ones(K))
+                s.set_stiffness(C)
+                extra = K * ANI_BYTES
+            s.set_dt(s.suggest_dt(w["cfl"]))
+            s.set_source(0, w["source"], w["f0"], w["t0"], w["amp"])
+            s.set_receivers(0, w["receivers"], 4096)
+            shape = s.autotune()
+            sec, _ = timed_steps(torch, s, stream, steps, warmup)
+            kms, _ = kernel_avg_ms(s)
+            s.close()
+        out[name] = {
+            "value": round(9 * Np * K * 5 * steps / sec / 1e9, 3),
+            "kernel_avg_ms": round(kms, 5),
+            "hbm_frac": round((stage_bytes(K, Np, 8) + extra) / (kms / 1e3) / 1e9
+                              / HBM_PEAK_GBS, 4),
+            "vs_plain": round(plain_ms / kms, 3),
+            "launch_shape": list(shape)}
+    return out
+
+
 def fwi_form(torch, stream, nsteps=600, iterations=3, prec=32):
     """The inversion loop (L-BFGS over the batched per-shot gradients) on
     the 24576-element order-3 workload: four shots in one batch, layered
@@ -461,6 +504,8 @@ def main():
                     "replay; lengths 500-2000 steps, all active in the window"}
         forms["order6"] = order6_form(torch, stream, w, max(20, args.steps // 5), 2)
         forms["general_mesh_fp64"] = general_mesh_form(
+            torch, stream, w, max(20, args.steps // 5), 2, kms)
+        forms["variants_fp64"] = variants_form(
             torch, stream, w, max(20, args.steps // 5), 2, kms)
         out["forms"] = forms
     if not args.no_adjoint:

@@ -239,6 +239,26 @@ int dgw_set_flux(dgw_ctx *ctx, double tau);
  * DGW_EINVAL for negative or non-finite rates. */
 int dgw_set_damping(dgw_ctx *ctx, const double *sigma);
 
+/* Anisotropic elements: per-element Voigt stiffness C [K][21], the upper
+ * triangle row by row (C11 C12 .. C16 C22 .. C66) in the order xx, yy, zz,
+ * yz, xz, xy with engineering shear strains; each C symmetric positive
+ * definite (DGW_EINVAL otherwise, or for non-finite values; the previous
+ * state is kept).  It replaces lambda and mu of dgw_set_material (rho
+ * stays): stress rate C e(v); at faces the exact Riemann states from the
+ * impedance matrices Z = (rho N(n)^T C N(n))^(1/2) of both sides,
+ * v* = (Z- + Z+)^-1 (Z- v- + Z+ v+ + t+ - t-), t* = t- + Z- (v* - v-)
+ * (N(n) maps a vector to the Voigt strain of its symmetric product with n;
+ * for isotropic C these are the isotropic states), blended with the central
+ * flux as set by dgw_set_flux; stress flux C N(n) dv.  Energy: the potential
+ * term uses the compliance C^-1.  dgw_suggest_dt uses the largest
+ * Christoffel speed over 258 sampled directions.  Runs on stage kernel 0
+ * (selected here; dgw_set_launch with kernel 1 is DGW_ESTATE while a
+ * stiffness is set); dgw_forward_checkpointed and dgw_adjoint are
+ * DGW_ESTATE.  A later dgw_set_material recomputes the impedances from the
+ * new rho.  NULL returns to isotropic elements.  Requires the mesh and the
+ * material (DGW_ESTATE).  Host data are copied. */
+int dgw_set_stiffness(dgw_ctx *ctx, const double *C);
+
 /* Launch shape of the stage kernel.  kernel 0: one thread per (element,
  * node) with the block's fields and lifted fluxes staged in LDS; then
  * elems_per_block is the elements per work-group (0 = default; DGW_EINVAL for

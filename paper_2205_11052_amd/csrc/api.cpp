@@ -526,6 +526,8 @@ int dgw_set_material(dgw_ctx *c, const double *rho, const double *lam,
   int rc = c->material_meta();
   if (rc) return rc;
   c->have_mat = true;
+  // the impedance matrices of anisotropic elements depend on rho
+  if (c->have_aniso && (rc = c->aniso_table())) return rc;
   return DGW_OK;
 }
 
@@ -538,7 +540,8 @@ int dgw_suggest_dt(const dgw_ctx *c, double cfl, double *dt_out) {
     double asum = 0;
     for (int f = 0; f < 4; ++f) asum += c->mesh.area[4 * k + f];
     const double rin = 3.0 * c->mesh.volume[k] / asum;
-    const double cp = std::sqrt((c->lam[k] + 2.0 * c->mu[k]) / c->rho[k]);
+    const double cp = c->have_aniso ? std::sqrt(c->aniso_max_speed2(k))
+                                    : std::sqrt((c->lam[k] + 2.0 * c->mu[k]) / c->rho[k]);
     best = std::min(best, rin / cp);
   }
   const int N = c->R.N;
@@ -761,7 +764,8 @@ int dgw_energy(dgw_ctx *c, int shot, double *E) {
   const size_t n = (size_t)c->mesh.K * 9 * c->R.Np;
   const char *q = (const char *)c->d_q[c->loc[shot]] + shot * n * c->real_size();
   hipError_t e = launch_energy(c->precision, q, c->mesh.K, c->R.Np, c->d_meta,
-                               c->d_M, c->d_partial, nb, c->stream);
+                               c->have_aniso ? c->d_aniso : nullptr, c->d_M,
+                               c->d_partial, nb, c->stream);
   if (e != hipSuccess) return c->hipfail(e, "energy kernel launch");
   std::vector<double> part(nb);
   int rc = c->download(part.data(), c->d_partial, sizeof(double) * nb);
@@ -818,6 +822,8 @@ int dgw_set_launch(dgw_ctx *c, int kernel, int elems_per_block, int wgs_per_cu) 
   if (!c) return DGW_EINVAL;
   if (!stage_kernel_supported(kernel, c->R.N, c->precision))
     return c->fail(DGW_EINVAL, "stage kernel not available for this order/precision");
+  if (kernel != 0 && c->have_aniso)
+    return c->fail(DGW_ESTATE, "anisotropic elements run on stage kernel 0 only");
   std::vector<int> ch = stage_block_choices(kernel, c->R.N, c->precision);
   if (elems_per_block == 0) elems_per_block = ch[0];
   if (std::find(ch.begin(), ch.end(), elems_per_block) == ch.end())

@@ -37,6 +37,9 @@ struct dgw_ctx {
   double flux_tau = 1.0;            // upwind weight of the face flux
   double *d_sponge = nullptr;       // [K] damping rate (sponge layer)
   bool have_sponge = false;
+  std::vector<double> aniso_C;      // [K][21] Voigt stiffness (upper), if set
+  double *d_aniso = nullptr;        // [K][DGW_ANI] anisotropic per-element data
+  bool have_aniso = false;
   std::vector<double> rho, lam, mu;
 
   // device data
@@ -98,6 +101,8 @@ struct dgw_ctx {
   int ensure_receivers(int need_r, int64_t need_cap);
   int clear_traces(int shot);
   int material_meta();
+  int aniso_table();                       // anisotropic per-element data
+  double aniso_max_speed2(int64_t k) const;  // of an anisotropic element
   int enqueue_step(int from, bool timed);
   int build_graph();
   int gather_shots_to_cur(const std::vector<int64_t> &adv);
@@ -131,6 +136,7 @@ inline void stage_args(const dgw_ctx *c, dgw::StageArgs<real> &a, const void *in
   a.src_par = c->d_src_par;
   a.ftau = (real)c->flux_tau;
   a.sponge = c->have_sponge ? c->d_sponge : nullptr;
+  a.aniso = c->have_aniso ? c->d_aniso : nullptr;
   a.rk_a = dgw::rk_a()[stage];
   a.rk_b = dgw::rk_b()[stage];
   a.rk_c = dgw::rk_c()[stage];

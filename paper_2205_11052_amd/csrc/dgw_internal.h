@@ -9,6 +9,7 @@
 
 #define DGW_MAX_ORDER 6
 #define DGW_META 48   // doubles of per-element data (see MetaLayout)
+#define DGW_ANI 120   // doubles of per-element anisotropic data (see AniLayout)
 
 namespace dgw {
 
@@ -26,6 +27,19 @@ enum MetaLayout {
   M_MU = 27, M_ZP = 28, M_ZS = 29, M_ZPNB = 30, M_ZSNB = 34, M_IZPS = 38,
   M_IZSS = 42, M_J = 46
 };
+
+// Per-element data of anisotropic elements, FP64, DGW_ANI doubles per
+// element (only when a stiffness is set):
+//   [0..20]   Voigt stiffness C (order xx yy zz yz xz xy, engineering
+//             shears), upper triangle row by row: C11 C12 .. C16 C22 .. C66
+//   [21 + 18 f ...] face f: Z- = (rho N^T C N)^(1/2) (own impedance matrix),
+//             W = (Z- + Z+)^-1, Z+ (the neighbour's, with the own normal;
+//             Z- on boundary faces); each symmetric 3x3 stored as
+//             (xx, yy, zz, yz, xz, xy)
+//   [93..113] Voigt compliance C^-1, upper triangle
+//   [114..119] unused
+enum AniLayout { A_C = 0, A_FACE = 21, A_FSTRIDE = 18, A_ZM = 0, A_W = 6, A_ZP = 12,
+                 A_S = 93 };
 
 // Packed face connectivity (int32 per element face): interior faces hold
 // (neighbour << 5) | (neighbour face << 3) | orientation (0..5); boundary
@@ -90,6 +104,7 @@ struct StageArgs {
   const double *src_par;        // [S][10]: moment[6], f0, t0, amp, unused
   real ftau;                    // weight of the upwind flux (1 - ftau: central)
   const double *sponge;         // [K] damping rate, or null
+  const double *aniso;          // [K][DGW_ANI] anisotropic data, or null
   double rk_a, rk_b, rk_c, dt;
 };
 
@@ -165,7 +180,8 @@ hipError_t launch_set_steps(int64_t *steps, int nshots, int64_t value,
 // Launchers (kernels.hip); return the launch error.
 // kernel 0 (one thread per element node on the vector ALUs) or 1 (the
 // volume and lift contractions as one GEMM on the matrix cores), both with
-// 256 threads per work-group: be = elements per work-group,
+// 256 threads per work-group; kernel 0 with args.aniso set runs the
+// anisotropic form, kernel 1 refuses it: be = elements per work-group,
 // wpc = persistent work-groups per compute unit (0: one work-group per block
 // of elements).  ncu = compute units.
 hipError_t launch_stage(int kernel, int N, int precision, int be, int wpc,
@@ -173,9 +189,10 @@ hipError_t launch_stage(int kernel, int N, int precision, int be, int wpc,
 bool stage_kernel_supported(int kernel, int N, int precision);
 hipError_t launch_receivers(int precision, int nshots, const RecArgs &a,
                             hipStream_t st);
+// aniso: [K][DGW_ANI] or null (isotropic elements)
 hipError_t launch_energy(int precision, const void *q, int64_t K, int Np,
-                         const double *meta, const double *M, double *partial,
-                         int nblocks, hipStream_t st);
+                         const double *meta, const double *aniso, const double *M,
+                         double *partial, int nblocks, hipStream_t st);
 hipError_t launch_finite(int precision, const void *q, int64_t n, int *flag,
                          hipStream_t st);
 // Supported elements-per-block values for an order / precision.

@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(256) receiver_kernel(RecArgs A) {
 template <typename real>
 __global__ void __launch_bounds__(256)
 energy_kernel(const real *q, int64_t K, int Np, const double *meta,
-              const double *M, double *partial) {
+              const double *aniso, const double *M, double *partial) {
   __shared__ double red[256];
   double acc = 0.0;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K;
@@ -57,6 +57,24 @@ energy_kernel(const real *q, int64_t K, int Np, const double *meta,
       }
     const double rho = g[47], la = g[M_LAM], mu = g[M_MU];
     const double kin = quad[0] + quad[1] + quad[2];
+    if (aniso) {
+      // anisotropic: sum_ab S_ab s_a^T M s_b with the compliance S = C^-1
+      const double *S = aniso + k * DGW_ANI + A_S;
+      double pot = 0.0;
+      int u = 0;
+      for (int a = 0; a < 6; ++a)
+        for (int b = a; b < 6; ++b, ++u) {
+          double x = 0.0;
+          for (int i = 0; i < Np; ++i) {
+            double mi = 0.0;
+            for (int j = 0; j < Np; ++j) mi += M[i * Np + j] * (double)qk[(3 + b) * Np + j];
+            x += (double)qk[(3 + a) * Np + i] * mi;
+          }
+          pot += (a == b ? 1.0 : 2.0) * S[u] * x;
+        }
+      acc += 0.5 * g[M_J] * (rho * kin + pot);
+      continue;
+    }
     // a fluid element (mu = 0) stores only the isotropic part,
     // tr^T M tr / (9 lambda): the mu -> 0 limit for isotropic stress
     const double pot =
@@ -95,14 +113,14 @@ hipError_t launch_receivers(int precision, int nshots, const RecArgs &a,
 }
 
 hipError_t launch_energy(int precision, const void *q, int64_t K, int Np,
-                         const double *meta, const double *M, double *partial,
-                         int nblocks, hipStream_t st) {
+                         const double *meta, const double *aniso, const double *M,
+                         double *partial, int nblocks, hipStream_t st) {
   if (precision == 64)
     hipLaunchKernelGGL(energy_kernel<double>, dim3(nblocks), dim3(256), 0, st,
-                       (const double *)q, K, Np, meta, M, partial);
+                       (const double *)q, K, Np, meta, aniso, M, partial);
   else
     hipLaunchKernelGGL(energy_kernel<float>, dim3(nblocks), dim3(256), 0, st,
-                       (const float *)q, K, Np, meta, M, partial);
+                       (const float *)q, K, Np, meta, aniso, M, partial);
   return hipGetLastError();
 }
 

@@ -18,8 +18,9 @@
 //      a per-face-node table, so no load waits on a table lookup) into
 //      registers;
 //   2. one thread per (element, face node): exact Riemann flux in jump form
-//      (optionally blended with the central flux) from the own trace (LDS)
-//      and the neighbour's (registers); six lifted
+//      (optionally blended with the central flux; for anisotropic elements
+//      from the face's impedance matrices, node-per-thread form only) from
+//      the own trace (LDS) and the neighbour's (registers); six lifted
 //      quantities go to LDS: the velocity flux and the velocity change dv,
 //      both times Fscale (the stress flux is lambda (n.dv) I + mu (dv n^T +
 //      n dv^T), n constant per face, so it is formed after lifting dv);
@@ -268,8 +269,11 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
   }
 }
 
-// Phase 3 on the vector ALUs: one thread per (element, node).
-template <int N, typename real, int BE>
+// Phase 3 on the vector ALUs: one thread per (element, node).  AN:
+// anisotropic elements, whose stress rate is C times the strain rate of the
+// volume term plus that of the lifted face terms (N(n_f) times the lifted
+// dv of each face), with C from the anisotropic per-element data.
+template <int N, typename real, int BE, bool AN>
 __device__ __forceinline__ void phase3_nodes(const StageArgs<real> &A, const real *sq,
                                              const real *sfl, const double *smeta,
                                              const double *ssig, int nE, int64_t k0,
@@ -319,17 +323,28 @@ __device__ __forceinline__ void phase3_nodes(const StageArgs<real> &A, const rea
       return X[b] * dr[c] + X[3 + b] * ds[c] + X[6 + b] * dt[c];
     };
     const real ri = (real)g[M_RHOINV], la = (real)g[M_LAM], mu = (real)g[M_MU];
-    const real divv = D(0, 0) + D(1, 1) + D(2, 2);
     real rhs[9];
     rhs[0] = (D(3, 0) + D(8, 1) + D(7, 2)) * ri;
     rhs[1] = (D(8, 0) + D(4, 1) + D(6, 2)) * ri;
     rhs[2] = (D(7, 0) + D(6, 1) + D(5, 2)) * ri;
-    rhs[3] = la * divv + 2 * mu * D(0, 0);
-    rhs[4] = la * divv + 2 * mu * D(1, 1);
-    rhs[5] = la * divv + 2 * mu * D(2, 2);
-    rhs[6] = mu * (D(1, 2) + D(2, 1));
-    rhs[7] = mu * (D(0, 2) + D(2, 0));
-    rhs[8] = mu * (D(0, 1) + D(1, 0));
+    // anisotropic: the Voigt strain rate (engineering shears), times C below
+    real ev[6];
+    if constexpr (AN) {
+      ev[0] = D(0, 0);
+      ev[1] = D(1, 1);
+      ev[2] = D(2, 2);
+      ev[3] = D(1, 2) + D(2, 1);
+      ev[4] = D(0, 2) + D(2, 0);
+      ev[5] = D(0, 1) + D(1, 0);
+    } else {
+      const real divv = D(0, 0) + D(1, 1) + D(2, 2);
+      rhs[3] = la * divv + 2 * mu * D(0, 0);
+      rhs[4] = la * divv + 2 * mu * D(1, 1);
+      rhs[5] = la * divv + 2 * mu * D(2, 2);
+      rhs[6] = mu * (D(1, 2) + D(2, 1));
+      rhs[7] = mu * (D(0, 2) + D(2, 0));
+      rhs[8] = mu * (D(0, 1) + D(1, 0));
+    }
     // lift: velocity flux over all faces; lifted dv per face, then the
     // stress components from it and the face normal
     const real *fle = sfl + e * NF * 6;
@@ -351,17 +366,43 @@ __device__ __forceinline__ void phase3_nodes(const StageArgs<real> &A, const rea
       }
       const real nx = (real)g[M_NORMAL + 3 * f], ny = (real)g[M_NORMAL + 3 * f + 1],
                  nz = (real)g[M_NORMAL + 3 * f + 2];
-      const real nU = nx * U0 + ny * U1 + nz * U2;
-      rhs[3] += la * nU + 2 * mu * U0 * nx;
-      rhs[4] += la * nU + 2 * mu * U1 * ny;
-      rhs[5] += la * nU + 2 * mu * U2 * nz;
-      rhs[6] += mu * (U1 * nz + U2 * ny);
-      rhs[7] += mu * (U0 * nz + U2 * nx);
-      rhs[8] += mu * (U0 * ny + U1 * nx);
+      if constexpr (AN) {
+        ev[0] += nx * U0;
+        ev[1] += ny * U1;
+        ev[2] += nz * U2;
+        ev[3] += nz * U1 + ny * U2;
+        ev[4] += nz * U0 + nx * U2;
+        ev[5] += ny * U0 + nx * U1;
+      } else {
+        const real nU = nx * U0 + ny * U1 + nz * U2;
+        rhs[3] += la * nU + 2 * mu * U0 * nx;
+        rhs[4] += la * nU + 2 * mu * U1 * ny;
+        rhs[5] += la * nU + 2 * mu * U2 * nz;
+        rhs[6] += mu * (U1 * nz + U2 * ny);
+        rhs[7] += mu * (U0 * nz + U2 * nx);
+        rhs[8] += mu * (U0 * ny + U1 * nx);
+      }
     }
     rhs[0] += V0;
     rhs[1] += V1;
     rhs[2] += V2;
+    if constexpr (AN) {
+      // stress rate C ev, C symmetric from its upper triangle
+      const double *Cu = A.aniso + k * DGW_ANI + A_C;
+      int u = 0;
+      real cm[6][6];
+#pragma unroll
+      for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = a; b < 6; ++b) cm[a][b] = cm[b][a] = (real)Cu[u++];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        real acc = 0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) acc += cm[a][b] * ev[b];
+        rhs[3 + a] = acc;
+      }
+    }
     if (A.sponge) {
       const real sg = (real)ssig[e];
 #pragma unroll
@@ -486,7 +527,7 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
   constexpr int FI = (BE * NF + kThreads - 1) / kThreads;   // face items per thread
   // declared here (not passed in) so every access stays an LDS access
   __shared__ real sq[BE * 9 * Np];
-  __shared__ __attribute__((aligned(16))) real sfl[BE * NF * (V == 0 ? 6 : 9)];
+  __shared__ __attribute__((aligned(16))) real sfl[BE * NF * (V == 1 ? 9 : 6)];
   __shared__ double smeta[BE * DGW_META];
   __shared__ double ssig[BE];
   const int shot = (int)(item / nblk);
@@ -581,32 +622,57 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
     const real dtx = dsxx * nx + dsxy * ny + dsxz * nz;
     const real dty = dsxy * nx + dsyy * ny + dsyz * nz;
     const real dtz = dsxz * nx + dsyz * ny + dszz * nz;
-    const real dvn = dvx * nx + dvy * ny + dvz * nz;
-    const real dtn = dtx * nx + dty * ny + dtz * nz;
-    const real zp = (real)g[M_ZP], zs = (real)g[M_ZS];
-    const real zpn = (real)g[M_ZPNB + f], zsn = (real)g[M_ZSNB + f];
-    const real izp = (real)g[M_IZPS + f], izs = (real)g[M_IZSS + f];
-    // normal and tangential Riemann amplitudes
-    const real kn = (dtn + zpn * dvn) * izp;
-    const real kTx = (dtx - dtn * nx + zsn * (dvx - dvn * nx)) * izs;
-    const real kTy = (dty - dtn * ny + zsn * (dvy - dvn * ny)) * izs;
-    const real kTz = (dtz - dtn * nz + zsn * (dvz - dvn * nz)) * izs;
     const real ri = (real)g[M_RHOINV], fs = (real)g[M_FSCALE + f];
-    // traction change t* - t- and velocity change dv = v* - v- of the flux
-    // states: tu times the exact Riemann states' plus (1 - tu) times the
-    // central states' (half the jumps); tu = 1 (upwind) leaves exactly the
-    // Riemann terms (1 x + 0 = x)
+    // traction change t* - t- (w) and velocity change dv = v* - v- (u) of
+    // the flux states: tu times the exact Riemann states' plus (1 - tu)
+    // times the central states' (half the jumps); tu = 1 (upwind) leaves
+    // exactly the Riemann terms (1 x + 0 = x)
     const real tu = A.ftau, hc = ((real)1 - tu) * (real)0.5;
-    const real wx = tu * (zp * kn * nx + zs * kTx) + hc * dtx;
-    const real wy = tu * (zp * kn * ny + zs * kTy) + hc * dty;
-    const real wz = tu * (zp * kn * nz + zs * kTz) + hc * dtz;
-    const real ux = tu * (kn * nx + kTx) + hc * dvx;
-    const real uy = tu * (kn * ny + kTy) + hc * dvy;
-    const real uz = tu * (kn * nz + kTz) + hc * dvz;
+    real wx, wy, wz, ux, uy, uz;
+    if constexpr (V == 2) {
+      // anisotropic: dv = W ([t] + Z+ [v]) and t* - t- = Z- dv with the
+      // face's impedance matrices (symmetric 3x3: xx yy zz yz xz xy)
+      const double *za = A.aniso + (k0 + e) * DGW_ANI + A_FACE + A_FSTRIDE * f;
+      auto smv = [](const double *Z, real x, real y, real z, real (&o)[3]) {
+        const real xx = (real)Z[0], yy = (real)Z[1], zz = (real)Z[2], yz = (real)Z[3],
+                   xz = (real)Z[4], xy = (real)Z[5];
+        o[0] = xx * x + xy * y + xz * z;
+        o[1] = xy * x + yy * y + yz * z;
+        o[2] = xz * x + yz * y + zz * z;
+      };
+      real zj[3], dv[3], dtr[3];
+      smv(za + A_ZP, dvx, dvy, dvz, zj);
+      smv(za + A_W, dtx + zj[0], dty + zj[1], dtz + zj[2], dv);
+      smv(za + A_ZM, dv[0], dv[1], dv[2], dtr);
+      wx = tu * dtr[0] + hc * dtx;
+      wy = tu * dtr[1] + hc * dty;
+      wz = tu * dtr[2] + hc * dtz;
+      ux = tu * dv[0] + hc * dvx;
+      uy = tu * dv[1] + hc * dvy;
+      uz = tu * dv[2] + hc * dvz;
+    } else {
+      const real dvn = dvx * nx + dvy * ny + dvz * nz;
+      const real dtn = dtx * nx + dty * ny + dtz * nz;
+      const real zp = (real)g[M_ZP], zs = (real)g[M_ZS];
+      const real zpn = (real)g[M_ZPNB + f], zsn = (real)g[M_ZSNB + f];
+      const real izp = (real)g[M_IZPS + f], izs = (real)g[M_IZSS + f];
+      // normal and tangential Riemann amplitudes
+      const real kn = (dtn + zpn * dvn) * izp;
+      const real kTx = (dtx - dtn * nx + zsn * (dvx - dvn * nx)) * izs;
+      const real kTy = (dty - dtn * ny + zsn * (dvy - dvn * ny)) * izs;
+      const real kTz = (dtz - dtn * nz + zsn * (dvz - dvn * nz)) * izs;
+      wx = tu * (zp * kn * nx + zs * kTx) + hc * dtx;
+      wy = tu * (zp * kn * ny + zs * kTy) + hc * dty;
+      wz = tu * (zp * kn * nz + zs * kTz) + hc * dtz;
+      ux = tu * (kn * nx + kTx) + hc * dvx;
+      uy = tu * (kn * ny + kTy) + hc * dvy;
+      uz = tu * (kn * nz + kTz) + hc * dvz;
+    }
     // velocity flux (t* - t-)/rho and the velocity change dv; the stress
-    // flux is lambda (n.dv) I + mu (dv n^T + n dv^T) with n constant on the
-    // face, so lifting dv is enough for all six stress components
-    if constexpr (V == 0) {
+    // flux is lambda (n.dv) I + mu (dv n^T + n dv^T) (anisotropic: C N(n) dv)
+    // with n constant on the face, so lifting dv is enough for all six
+    // stress components
+    if constexpr (V != 1) {
       real *d = sfl + (e * NF + fm) * 6;
       d[0] = fs * wx * ri;
       d[1] = fs * wy * ri;
@@ -637,8 +703,8 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
   if constexpr (V == 1)
     phase3_mfma<N, real, BE>(A, sq, sfl, smeta, ssig, nE, k0, shot, step, qout, res, oz, tid);
   else
-    phase3_nodes<N, real, BE>(A, sq, sfl, smeta, ssig, nE, k0, shot, step, qout, res, oz,
-                              tid);
+    phase3_nodes<N, real, BE, V == 2>(A, sq, sfl, smeta, ssig, nE, k0, shot, step, qout,
+                                      res, oz, tid);
 }
 
 // One work-group per item.
@@ -682,8 +748,8 @@ template <int N, typename real, int V>
 struct Shapes {
   static constexpr int Np = Sz<N>::Np, NF = 4 * Sz<N>::Nfp;
   static constexpr int per =
-      (9 * Np + (V == 0 ? 6 : 9) * NF) * (int)sizeof(real) + DGW_META * 8;
-  static constexpr int cap1 = V == 0 ? kThreads / Np : kThreads / 64 * 16 / 9;
+      (9 * Np + (V == 1 ? 9 : 6) * NF) * (int)sizeof(real) + DGW_META * 8;
+  static constexpr int cap1 = V != 1 ? kThreads / Np : kThreads / 64 * 16 / 9;
   static constexpr int cap2 = 65536 / per;
   static constexpr int a = cap1 < cap2 ? cap1 : cap2;
   static constexpr int b = a / 2 > 0 ? a / 2 : 1;
@@ -751,6 +817,14 @@ std::vector<int> choices_r(int N) {
 hipError_t launch_stage(int kernel, int N, int precision, int be, int wpc, int ncu,
                         int nshots, const void *args, hipStream_t st) {
   if (!stage_kernel_supported(kernel, N, precision)) return hipErrorInvalidValue;
+  // anisotropic elements: the node-per-thread form only
+  const bool an = precision == 64 ? ((const StageArgs<double> *)args)->aniso != nullptr
+                                  : ((const StageArgs<float> *)args)->aniso != nullptr;
+  if (an) {
+    if (kernel != 0) return hipErrorInvalidValue;
+    return precision == 64 ? launch_r<double, 2>(N, be, wpc, ncu, nshots, args, st)
+                           : launch_r<float, 2>(N, be, wpc, ncu, nshots, args, st);
+  }
   if (precision == 64)
     return kernel == 0 ? launch_r<double, 0>(N, be, wpc, ncu, nshots, args, st)
                        : launch_r<double, 1>(N, be, wpc, ncu, nshots, args, st);

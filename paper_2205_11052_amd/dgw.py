@@ -204,8 +204,19 @@ class Solver:
         self.set_mesh(mesh["vxyz"], mesh["etov"], mesh.get("vertex_periodic_id"),
                       mesh.get("face_bc"))
 
+    def _per_element(self, a, width, name):
+        """FP64 host copy of a per-element array; the library reads exactly
+        K * width values, so any other size is refused here (before the
+        mesh is set the library reads none and reports the call order)."""
+        a = _host64(a)
+        if self.K > 0 and a.size != self.K * width:
+            raise ValueError("%s must hold %d values per element (%d elements), got %d"
+                             % (name, width, self.K, a.size))
+        return a
+
     def set_material(self, rho, lam, mu):
-        r, l, m = _host64(rho), _host64(lam), _host64(mu)
+        r, l, m = (self._per_element(a, 1, n)
+                   for a, n in ((rho, "rho"), (lam, "lambda"), (mu, "mu")))
         self._check(self.lib.dgw_set_material(self._ctx, _dptr(r), _dptr(l),
                                               _dptr(m)), "dgw_set_material")
 
@@ -317,8 +328,26 @@ class Solver:
         if sigma is None:
             self._check(self.lib.dgw_set_damping(self._ctx, None), "dgw_set_damping")
             return
-        sg = _host64(sigma)
+        sg = self._per_element(sigma, 1, "sigma")
         self._check(self.lib.dgw_set_damping(self._ctx, _dptr(sg)), "dgw_set_damping")
+
+    def set_stiffness(self, C=None):
+        """Anisotropic elements: Voigt stiffness per element, [K, 6, 6]
+        (symmetric) or its upper triangles [K, 21] (None: isotropic
+        again)."""
+        if C is None:
+            self._check(self.lib.dgw_set_stiffness(self._ctx, None), "dgw_set_stiffness")
+            return
+        C = np.asarray(C, dtype=np.float64)
+        if C.ndim == 3:
+            if C.shape[1:] != (6, 6):
+                raise ValueError("stiffness must be [K, 6, 6] or [K, 21]")
+            iu = np.triu_indices(6)
+            C = C[:, iu[0], iu[1]]
+        if C.ndim != 2 or C.shape[1] != 21:
+            raise ValueError("stiffness must be [K, 6, 6] or [K, 21]")
+        up = self._per_element(C, 21, "stiffness")
+        self._check(self.lib.dgw_set_stiffness(self._ctx, _dptr(up)), "dgw_set_stiffness")
 
     def set_flux(self, tau=1.0):
         """Upwind weight of the face flux (1 upwind, 0 central)."""

@@ -158,3 +158,18 @@ def test_energy_matrix_upwind_dissipates_central_conserves(N, periodic):
             # the central flux exchanges no energy across interior faces,
             # and none at free-surface or absorbing ghost states either
             assert np.abs(ev).max() <= 1e-11 * scale, (periodic, np.abs(ev).max() / scale)
+
+
+def test_set_stiffness_checks_on_host():
+    import ctypes as Ct
+    from paper_2205_11052_amd import _lib
+    lib = _lib.load()
+    ctx = Ct.c_void_p()
+    assert lib.dgw_create(3, 64, 1, None, Ct.byref(ctx)) == 0
+    try:
+        up = (Ct.c_double * 21)(*W.stiffness_upper(W.isotropic_stiffness(1.0, 1.0))[0])
+        assert lib.dgw_set_stiffness(None, up) == -1
+        assert lib.dgw_set_stiffness(ctx, up) == -5      # no mesh yet
+        assert lib.dgw_set_stiffness(ctx, None) == -5
+    finally:
+        lib.dgw_destroy(ctx)
