@@ -1,7 +1,7 @@
 /*
- * dgw -- nodal discontinuous Galerkin solver for the isotropic
- * velocity-stress elastic wave equation on affine tetrahedra, for AMD
- * Instinct MI355X (gfx950).
+ * dgw -- nodal discontinuous Galerkin solver for the isotropic (optionally
+ * anisotropic, dgw_set_stiffness) velocity-stress elastic wave equation on
+ * affine tetrahedra, for AMD Instinct MI355X (gfx950).
  *
  * Method.  The paper this library accompanies (arXiv 2205.11052) does not
  * describe the discretisation, so every entry point states what it computes:
@@ -251,9 +251,8 @@ int dgw_set_damping(dgw_ctx *ctx, const double *sigma);
  * for isotropic C these are the isotropic states), blended with the central
  * flux as set by dgw_set_flux; stress flux C N(n) dv.  Energy: the potential
  * term uses the compliance C^-1.  dgw_suggest_dt uses the largest
- * Christoffel speed over 258 sampled directions.  Runs on stage kernel 0
- * (selected here; dgw_set_launch with kernel 1 is DGW_ESTATE while a
- * stiffness is set); dgw_forward_checkpointed and dgw_adjoint are
+ * Christoffel speed over 258 sampled directions.  Both stage kernels
+ * have an anisotropic form; dgw_forward_checkpointed and dgw_adjoint are
  * DGW_ESTATE.  A later dgw_set_material recomputes the impedances from the
  * new rho.  NULL returns to isotropic elements.  Requires the mesh and the
  * material (DGW_ESTATE).  Host data are copied. */

@@ -287,10 +287,5 @@ extern "C" int dgw_set_stiffness(dgw_ctx *c, const double *C) {
     return rc;
   }
   c->have_aniso = true;
-  if (c->kernel != 0) {
-    // the matrix-core form is isotropic only
-    c->kernel = 0;
-    c->block = default_block(0, c->R.N, c->precision);
-  }
   return DGW_OK;
 }

@@ -822,8 +822,6 @@ int dgw_set_launch(dgw_ctx *c, int kernel, int elems_per_block, int wgs_per_cu) 
   if (!c) return DGW_EINVAL;
   if (!stage_kernel_supported(kernel, c->R.N, c->precision))
     return c->fail(DGW_EINVAL, "stage kernel not available for this order/precision");
-  if (kernel != 0 && c->have_aniso)
-    return c->fail(DGW_ESTATE, "anisotropic elements run on stage kernel 0 only");
   std::vector<int> ch = stage_block_choices(kernel, c->R.N, c->precision);
   if (elems_per_block == 0) elems_per_block = ch[0];
   if (std::find(ch.begin(), ch.end(), elems_per_block) == ch.end())

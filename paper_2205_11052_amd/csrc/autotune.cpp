@@ -76,9 +76,8 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *kernel,
                 (long long)c->mesh.K, c->nshots, c->have_aniso ? "_aniso" : "");
   std::vector<Shape> opts;
   for (int kv : {0, 1})
-    if (kv == 0 || !c->have_aniso)   // anisotropic elements: kernel 0 only
-      for (int be : stage_block_choices(kv, c->R.N, c->precision))
-        for (int w : {0, 1, 2, 3, 4, 8, 16}) opts.push_back({kv, be, w});
+    for (int be : stage_block_choices(kv, c->R.N, c->precision))
+      for (int w : {0, 1, 2, 3, 4, 8, 16}) opts.push_back({kv, be, w});
   auto report = [&](const Shape &o) {
     if (kernel) *kernel = o.kernel;
     if (elems_per_block) *elems_per_block = o.be;

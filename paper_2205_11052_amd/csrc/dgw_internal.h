@@ -180,8 +180,8 @@ hipError_t launch_set_steps(int64_t *steps, int nshots, int64_t value,
 // Launchers (kernels.hip); return the launch error.
 // kernel 0 (one thread per element node on the vector ALUs) or 1 (the
 // volume and lift contractions as one GEMM on the matrix cores), both with
-// 256 threads per work-group; kernel 0 with args.aniso set runs the
-// anisotropic form, kernel 1 refuses it: be = elements per work-group,
+// 256 threads per work-group; with args.aniso set each runs its
+// anisotropic form: be = elements per work-group,
 // wpc = persistent work-groups per compute unit (0: one work-group per block
 // of elements).  ncu = compute units.
 hipError_t launch_stage(int kernel, int N, int precision, int be, int wpc,

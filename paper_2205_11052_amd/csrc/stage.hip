@@ -19,8 +19,8 @@
 //      registers;
 //   2. one thread per (element, face node): exact Riemann flux in jump form
 //      (optionally blended with the central flux; for anisotropic elements
-//      from the face's impedance matrices, node-per-thread form only) from
-//      the own trace (LDS) and the neighbour's (registers); six lifted
+//      from the face's impedance matrices) from the own trace (LDS) and the
+//      neighbour's (registers); six lifted
 //      quantities go to LDS: the velocity flux and the velocity change dv,
 //      both times Fscale (the stress flux is lambda (n.dv) I + mu (dv n^T +
 //      n dv^T), n constant per face, so it is formed after lifting dv);
@@ -106,7 +106,7 @@ struct Mma<double> {
 // (element, field); rows are nodes.  The accumulators go through LDS (the
 // flux buffer, dead by then) so that the residual loads, the update and the
 // stores run over the block's contiguous span, fully coalesced.
-template <int N, typename real, int BE>
+template <int N, typename real, int BE, bool AN>
 __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real *sq,
                                             real *sfl, const double *smeta,
                                             const double *ssig, int nE,
@@ -153,8 +153,8 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
     // 0 1/rho, 1 lambda + 2 mu, 2 lambda, 3 mu, 4 zero)
     constexpr uint32_t X0 = 0x1a000u, X1 = 0x01555u, X2 = 0x2aaaau;
     constexpr uint32_t S0 = 0x36d2200u, S1 = 0x36d1400u, S2 = 0x490a400u;
-    const int f0 = (int)((F0 >> (4 * k)) & 15), f1 = (int)((F1 >> (4 * k)) & 15),
-              f2 = (int)((F2 >> (4 * k)) & 15);
+    int f0 = (int)((F0 >> (4 * k)) & 15), f1 = (int)((F1 >> (4 * k)) & 15),
+        f2 = (int)((F2 >> (4 * k)) & 15);
     const real ri = (real)gm[M_RHOINV], la = (real)gm[M_LAM], mu = (real)gm[M_MU];
     const real l2 = la + 2 * mu;
     auto fac = [&](uint32_t S) -> real {
@@ -173,6 +173,33 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
       c[a][0] = s0 * pick(x0);
       c[a][1] = s1 * pick(x1);
       c[a][2] = s2 * pick(x2);
+    }
+    if constexpr (AN) {
+      // anisotropic stress rows (k >= 3, Voigt row I = k - 3): the fields
+      // are (vx, vy, vz) and c[a][m] = sum_b C[I][voigt(m, b)] X^-1[a][b]
+      // (selects, so the column setup stays branch-free)
+      const bool st = k >= 3;
+      const int I = st ? k - 3 : 0;
+      const double *Cu = A.aniso + (k0 + e) * DGW_ANI + A_C;
+      real cr[6];
+#pragma unroll
+      for (int J = 0; J < 6; ++J) {
+        const int i = I < J ? I : J, j = I < J ? J : I;   // upper triangle
+        cr[J] = (real)Cu[i * (11 - i) / 2 + j];
+      }
+      constexpr int VG[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};   // voigt(m, b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          real v = 0;
+#pragma unroll
+          for (int b = 0; b < 3; ++b) v += cr[VG[m][b]] * (real)gm[M_XINV + 3 * a + b];
+          c[a][m] = st ? v : c[a][m];
+        }
+      f0 = st ? 0 : f0;
+      f1 = st ? 1 : f1;
+      f2 = st ? 2 : f2;
     }
     const real *q0 = qe + f0 * Np, *q1 = qe + f1 * Np, *q2 = qe + f2 * Np;
     v4 *ac = acc[ntl];
@@ -527,7 +554,7 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
   constexpr int FI = (BE * NF + kThreads - 1) / kThreads;   // face items per thread
   // declared here (not passed in) so every access stays an LDS access
   __shared__ real sq[BE * 9 * Np];
-  __shared__ __attribute__((aligned(16))) real sfl[BE * NF * (V == 1 ? 9 : 6)];
+  __shared__ __attribute__((aligned(16))) real sfl[BE * NF * (V == 1 || V == 3 ? 9 : 6)];
   __shared__ double smeta[BE * DGW_META];
   __shared__ double ssig[BE];
   const int shot = (int)(item / nblk);
@@ -629,7 +656,7 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
     // exactly the Riemann terms (1 x + 0 = x)
     const real tu = A.ftau, hc = ((real)1 - tu) * (real)0.5;
     real wx, wy, wz, ux, uy, uz;
-    if constexpr (V == 2) {
+    if constexpr (V == 2 || V == 3) {
       // anisotropic: dv = W ([t] + Z+ [v]) and t* - t- = Z- dv with the
       // face's impedance matrices (symmetric 3x3: xx yy zz yz xz xy)
       const double *za = A.aniso + (k0 + e) * DGW_ANI + A_FACE + A_FSTRIDE * f;
@@ -672,7 +699,7 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
     // flux is lambda (n.dv) I + mu (dv n^T + n dv^T) (anisotropic: C N(n) dv)
     // with n constant on the face, so lifting dv is enough for all six
     // stress components
-    if constexpr (V != 1) {
+    if constexpr (V == 0 || V == 2) {
       real *d = sfl + (e * NF + fm) * 6;
       d[0] = fs * wx * ri;
       d[1] = fs * wy * ri;
@@ -682,26 +709,47 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
       d[5] = fs * uz;
     } else {
       // all nine lifted components, field-major (the GEMM's data side)
-      const real la = (real)g[M_LAM], mu = (real)g[M_MU];
       const real Dvx = fs * ux, Dvy = fs * uy, Dvz = fs * uz;
-      const real ndv = nx * Dvx + ny * Dvy + nz * Dvz;
       real *d = sfl + e * 9 * NF + fm;
       d[0 * NF] = fs * wx * ri;
       d[1 * NF] = fs * wy * ri;
       d[2 * NF] = fs * wz * ri;
-      d[3 * NF] = la * ndv + 2 * mu * Dvx * nx;
-      d[4 * NF] = la * ndv + 2 * mu * Dvy * ny;
-      d[5 * NF] = la * ndv + 2 * mu * Dvz * nz;
-      d[6 * NF] = mu * (Dvy * nz + Dvz * ny);
-      d[7 * NF] = mu * (Dvx * nz + Dvz * nx);
-      d[8 * NF] = mu * (Dvx * ny + Dvy * nx);
+      if constexpr (V == 3) {
+        // C N(n) dv
+        const real ev[6] = {nx * Dvx, ny * Dvy, nz * Dvz, nz * Dvy + ny * Dvz,
+                            nz * Dvx + nx * Dvz, ny * Dvx + nx * Dvy};
+        const double *Cu = A.aniso + (k0 + e) * DGW_ANI + A_C;
+        real cm[6][6];
+        int uu = 0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+          for (int b = a; b < 6; ++b) cm[a][b] = cm[b][a] = (real)Cu[uu++];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+          real acc = 0;
+#pragma unroll
+          for (int b = 0; b < 6; ++b) acc += cm[a][b] * ev[b];
+          d[(3 + a) * NF] = acc;
+        }
+      } else {
+        const real la = (real)g[M_LAM], mu = (real)g[M_MU];
+        const real ndv = nx * Dvx + ny * Dvy + nz * Dvz;
+        d[3 * NF] = la * ndv + 2 * mu * Dvx * nx;
+        d[4 * NF] = la * ndv + 2 * mu * Dvy * ny;
+        d[5 * NF] = la * ndv + 2 * mu * Dvz * nz;
+        d[6 * NF] = mu * (Dvy * nz + Dvz * ny);
+        d[7 * NF] = mu * (Dvx * nz + Dvz * nx);
+        d[8 * NF] = mu * (Dvx * ny + Dvy * nx);
+      }
     }
   }
   __syncthreads();
 
 
-  if constexpr (V == 1)
-    phase3_mfma<N, real, BE>(A, sq, sfl, smeta, ssig, nE, k0, shot, step, qout, res, oz, tid);
+  if constexpr (V == 1 || V == 3)
+    phase3_mfma<N, real, BE, V == 3>(A, sq, sfl, smeta, ssig, nE, k0, shot, step, qout, res,
+                                     oz, tid);
   else
     phase3_nodes<N, real, BE, V == 2>(A, sq, sfl, smeta, ssig, nE, k0, shot, step, qout,
                                       res, oz, tid);
@@ -748,8 +796,9 @@ template <int N, typename real, int V>
 struct Shapes {
   static constexpr int Np = Sz<N>::Np, NF = 4 * Sz<N>::Nfp;
   static constexpr int per =
-      (9 * Np + (V == 1 ? 9 : 6) * NF) * (int)sizeof(real) + DGW_META * 8;
-  static constexpr int cap1 = V != 1 ? kThreads / Np : kThreads / 64 * 16 / 9;
+      (9 * Np + (V == 1 || V == 3 ? 9 : 6) * NF) * (int)sizeof(real) + DGW_META * 8;
+  static constexpr int cap1 =
+      V == 0 || V == 2 ? kThreads / Np : kThreads / 64 * 16 / 9;
   static constexpr int cap2 = 65536 / per;
   static constexpr int a = cap1 < cap2 ? cap1 : cap2;
   static constexpr int b = a / 2 > 0 ? a / 2 : 1;
@@ -771,7 +820,8 @@ hipError_t launch_t(int be, int wpc, int ncu, int nshots, const StageArgs<real> 
                     hipStream_t st) {
   constexpr int A_ = Shapes<N, real, V>::a, B_ = Shapes<N, real, V>::b;
   if (be != A_ && be != B_) return hipErrorInvalidValue;
-  if (V == 1 && (a.Avol == nullptr || a.Alift == nullptr)) return hipErrorInvalidValue;
+  if ((V == 1 || V == 3) && (a.Avol == nullptr || a.Alift == nullptr))
+    return hipErrorInvalidValue;
   const int64_t nblk = (a.K + be - 1) / be;
   const int64_t total = nblk * nshots;
   const int64_t pers = ((int64_t)ncu * wpc + 7) / 8 * 8;
@@ -817,13 +867,16 @@ std::vector<int> choices_r(int N) {
 hipError_t launch_stage(int kernel, int N, int precision, int be, int wpc, int ncu,
                         int nshots, const void *args, hipStream_t st) {
   if (!stage_kernel_supported(kernel, N, precision)) return hipErrorInvalidValue;
-  // anisotropic elements: the node-per-thread form only
+  // anisotropic elements: instantiations 2 (node per thread) and 3 (matrix
+  // cores)
   const bool an = precision == 64 ? ((const StageArgs<double> *)args)->aniso != nullptr
                                   : ((const StageArgs<float> *)args)->aniso != nullptr;
   if (an) {
-    if (kernel != 0) return hipErrorInvalidValue;
-    return precision == 64 ? launch_r<double, 2>(N, be, wpc, ncu, nshots, args, st)
-                           : launch_r<float, 2>(N, be, wpc, ncu, nshots, args, st);
+    if (precision == 64)
+      return kernel == 0 ? launch_r<double, 2>(N, be, wpc, ncu, nshots, args, st)
+                         : launch_r<double, 3>(N, be, wpc, ncu, nshots, args, st);
+    return kernel == 0 ? launch_r<float, 2>(N, be, wpc, ncu, nshots, args, st)
+                       : launch_r<float, 3>(N, be, wpc, ncu, nshots, args, st);
   }
   if (precision == 64)
     return kernel == 0 ? launch_r<double, 0>(N, be, wpc, ncu, nshots, args, st)

@@ -4,7 +4,7 @@ the same stiffness: FP64 relative L2 <= 1e-12, FP32 <= 1e-5, fully
 anisotropic heterogeneous media (every one of the 21 entries nonzero and
 varying per element), every boundary type, blended flux, a moment source
 and receivers; a general mesh; the full 82944-element order-4 mesh in the
-benchmark's node-per-thread launch shapes; the device energy; an isotropic
+benchmark's launch shapes of both kernels; the device energy; an isotropic
 C against the isotropic path; the state rules of the entry point.
 """
 
@@ -64,12 +64,14 @@ def _run_case(mesh, N, prec, tau, seed, nst=6, shape=(0, 0, 0)):
     return s, P, rho, q_ora, tr_ora
 
 
+@pytest.mark.parametrize("kernel", [0, 1])
 @pytest.mark.parametrize("N,prec,tau", [(2, 64, 1.0), (3, 64, 1.0), (4, 64, 1.0),
                                         (4, 64, 0.5), (4, 32, 1.0), (3, 32, 0.0)])
-def test_anisotropic_matches_oracle(N, prec, tau):
+def test_anisotropic_matches_oracle(N, prec, tau, kernel):
     mesh = W.kuhn_cube(3, 1.0)                 # free-surface top, absorbing sides
-    say("case aniso N=%d fp%d tau=%.1f" % (N, prec, tau))
-    s, P, rho, q_ora, tr_ora = _run_case(mesh, N, prec, tau, 70 + N)
+    say("case aniso N=%d fp%d tau=%.1f kernel=%d" % (N, prec, tau, kernel))
+    s, P, rho, q_ora, tr_ora = _run_case(mesh, N, prec, tau, 70 + N,
+                                         shape=(kernel, 0, 0))
     err = rel_l2(s.get_fields(0), q_ora)
     terr = rel_l2(s.read_traces(0), tr_ora)
     say("aniso fields %.3e traces %.3e" % (err, terr))
@@ -83,11 +85,12 @@ def test_anisotropic_matches_oracle(N, prec, tau):
         assert abs(s.energy(0) - e_ora) <= 1e-13 * e_ora
 
 
-def test_anisotropic_general_mesh():
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_anisotropic_general_mesh(kernel):
     g = W.general_mesh(4, 2.0, seed=77)
     mesh = permute_mesh(g, order_elements(g["vxyz"], g["etov"], "morton"))
-    say("case aniso general mesh K=%d" % mesh["etov"].shape[0])
-    s, P, rho, q_ora, tr_ora = _run_case(mesh, 3, 64, 1.0, 90)
+    say("case aniso general mesh K=%d kernel=%d" % (mesh["etov"].shape[0], kernel))
+    s, P, rho, q_ora, tr_ora = _run_case(mesh, 3, 64, 1.0, 90, shape=(kernel, 0, 0))
     err = rel_l2(s.get_fields(0), q_ora)
     terr = rel_l2(s.read_traces(0), tr_ora)
     say("aniso general mesh fields %.3e traces %.3e" % (err, terr))
@@ -96,8 +99,8 @@ def test_anisotropic_general_mesh():
 
 def test_full_size_anisotropic_fp64():
     """The 82944-element order-4 mesh with a fully anisotropic heterogeneous
-    medium, two steps against the oracle in the node-per-thread launch
-    shapes (one work-group per block, both block sizes, persistent)."""
+    medium, two steps against the oracle in both kernels' launch shapes
+    (one work-group per block, both block sizes, persistent)."""
     mesh = W.kuhn_cube(24, 10.0)
     K = mesh["etov"].shape[0]
     say("case full aniso K=%d" % K)
@@ -109,7 +112,7 @@ def test_full_size_anisotropic_fp64():
     one = np.ones(K)
     q_ora, _ = oracle_run(P, q0, rho, one, one, dt, 2)
     s = _solver(mesh, 4, rho, C, dt)
-    for shape in ((0, 7, 0), (0, 3, 0), (0, 7, 3)):
+    for shape in ((1, 7, 0), (1, 3, 0), (1, 7, 3), (0, 7, 0), (0, 3, 0), (0, 7, 3)):
         s.set_launch(*shape)
         s.set_fields(0, q0)
         s.step(2)
@@ -158,10 +161,7 @@ def test_state_rules():
     assert e.value.code == -5
     s.set_material(rho, np.ones(K), np.ones(K))
     s.set_launch(1)
-    s.set_stiffness(C)                           # selects kernel 0
-    with pytest.raises(DGWError) as e:
-        s.set_launch(1)
-    assert e.value.code == -5
+    s.set_stiffness(C)
     bad = C.copy()
     bad[3] = -np.eye(6)
     with pytest.raises(DGWError) as e:
