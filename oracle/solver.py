@@ -33,11 +33,11 @@ Semi-discrete strong form (nodal DG; Hesthaven and Warburton 2008):
   right-hand side gains -sigma_k q on every field of element k, the
   damping layer of Cerjan, Kosloff, Kosloff and Reshef (Geophysics 50,
   1985); the energy then changes by -2 sum_k sigma_k E_k.
-* fluid elements (mu = 0, acoustic; row f3): Zs = 0, so the tangential
+* fluid elements (mu = 0, acoustic): Zs = 0, so the tangential
   states above are well defined whenever one side is solid (the solid's
   tangential traction acts on a slip interface); where both sides are fluid
   (Zs- + Zs+ = 0) there is no tangential coupling: t*_T = t-_T, v*_T = v-_T.
-* anisotropic elements (P.stiffness = C [K, 6, 6], default none; row f3):
+* anisotropic elements (P.stiffness = C [K, 6, 6], default none):
   the stiffness in Voigt order (xx, yy, zz, yz, xz, xy) with engineering
   shear strains, symmetric positive definite, replaces lambda and mu
   (rho stays).  Volume: sigma_t = C e(v) with
