@@ -326,6 +326,51 @@ def variants_form(torch, stream, w, steps, warmup, plain_ms):
     return out
 
 
+def batched_gradients_form(torch, stream, w, nshots=8, scale=10, ckpt=25):
+    """Per-shot gradients of a batch: the first 8 of the 32 batched shots
+    (seeded positions in the upper half, uneven lengths 500-2000 steps,
+    here divided by 10) on the benchmark's mesh and layered medium
+    (82944 elements, order 4, FP32), all in one batch: forward with
+    checkpoints every 25 steps plus the reverse sweep, each shot over its
+    own length, observed data zero (misfit 1/2 dt sum trace^2).  Seconds
+    for the whole batch and per shot-step."""
+    import workloads as W
+    from paper_2205_11052_amd import Solver
+    pos, lens = W.batched_shots()
+    pos, lens = pos[:nshots], np.maximum(lens[:nshots] // scale, 1)
+    nsteps = int(lens.max())
+    with torch.cuda.stream(stream):
+        s = Solver(w["N"], 32, nshots, stream=stream.cuda_stream)
+        s.set_mesh_dict(w["mesh"])
+        s.set_material(w["rho"], w["lam"], w["mu"])
+        s.set_dt(s.suggest_dt(w["cfl"]))
+        for i in range(nshots):
+            s.set_source(i, pos[i], w["f0"], w["t0"], w["amp"], nsteps=int(lens[i]))
+            s.set_receivers(i, w["receivers"], nsteps)
+        s.autotune()
+        R = len(w["receivers"])
+        s.zero_fields()                                  # warm-up (2 steps)
+        s.forward_checkpointed(2, 1, np.zeros((nshots, R, 3, 2)))
+        s.adjoint()
+        d = np.zeros((nshots, R, 3, nsteps))
+        s.zero_fields()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mis = s.forward_checkpointed(nsteps, ckpt, d)
+        g = s.adjoint()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        s.close()
+    finite = all(np.isfinite(x).all() for x in g) and np.isfinite(mis).all()
+    return {"shots": nshots, "lengths": [int(x) for x in lens],
+            "precision": "fp32", "checkpoint_every": ckpt,
+            "elements": w["K"], "order": w["N"],
+            "s_total": round(sec, 3),
+            "ms_per_shot_step": round(1e3 * sec / float(lens.sum()), 3),
+            "gradients_finite": bool(finite),
+            "grad_rho_norm_per_shot": [float(np.linalg.norm(g[0][i])) for i in range(nshots)]}
+
+
 def fwi_form(torch, stream, nsteps=600, iterations=3, prec=32):
     """The inversion loop (L-BFGS over the batched per-shot gradients) on
     the 24576-element order-3 workload: four shots in one batch, layered
@@ -510,6 +555,7 @@ def main():
         out["forms"] = forms
     if not args.no_adjoint:
         out["adjoint"] = adjoint_form(torch, stream)
+        out["batched_gradients"] = batched_gradients_form(torch, stream, w)
         out["fwi"] = fwi_form(torch, stream)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
