@@ -333,8 +333,10 @@ def batched_gradients_form(torch, stream, w, nshots=8, scale=4, ckpt=25, t0=0.1)
     medium (82944 elements, order 4, FP32), all in one batch: forward with
     checkpoints every 25 steps plus the reverse sweep, each shot over its
     own length, observed data zero (misfit 1/2 dt sum trace^2), Ricker
-    delay t0 = 0.1 so the wavelet acts within the shortened window.
-    Seconds for the whole batch and per shot-step."""
+    delay t0 = 0.1 so the wavelet acts within the shortened window (shots
+    whose waves have not reached the surface receivers yet have tiny
+    misfits: the form measures time).  Seconds for the whole batch and per
+    shot-step."""
     import workloads as W
     from paper_2205_11052_amd import Solver
     pos, lens = W.batched_shots()
