@@ -211,6 +211,16 @@ int dgw_forward_checkpointed(dgw_ctx *ctx, int64_t nsteps, int64_t ckpt_every,
                              const double *d_obs, double *misfit);
 int dgw_adjoint(dgw_ctx *ctx, double *g_rho, double *g_lam, double *g_mu);
 
+/* Device memory the reverse sweep of dgw_adjoint may spend on keeping the
+ * inner stage states of a checkpoint segment (ckpt_every x 4 states of all
+ * shots): within the budget, the states the segment's recomputation
+ * produces are kept and each reverse step reads them; otherwise each
+ * reverse step recomputes its four inner stages from the step start.  The
+ * results are identical either way.  bytes = -1 (the default) takes a
+ * quarter of the free device memory at the call; 0 never keeps them.
+ * DGW_EINVAL for bytes < -1. */
+int dgw_set_adjoint_memory(dgw_ctx *ctx, int64_t bytes);
+
 /* Time the available launch shapes of the stage kernel on this context's
  * workload (real stage launches into scratch buffers; the solver state is not
  * changed) and keep the fastest; if cache_path is not NULL the choice is read

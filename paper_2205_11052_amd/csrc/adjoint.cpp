@@ -248,10 +248,27 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
   void *lq = alloc(n), *lr = alloc(n), *res = alloc(n);
   void *zbuf = alloc((size_t)c->nshots * K * 9 * NF * rs);
   double *grad = (double *)alloc(sizeof(double) * c->nshots * K * 3);
-  void *st[5] = {nullptr, alloc(n), alloc(n), alloc(n), alloc(n)};
+  // Keep the four inner stage states of every step of a segment when the
+  // memory budget allows (every x 4 more states): the segment recompute
+  // writes them anyway, and the reverse step then reads them instead of
+  // recomputing four stages.  Otherwise only the step-start states are kept.
+  size_t budget;
+  if (c->adj_budget >= 0) {
+    budget = (size_t)c->adj_budget;
+  } else {
+    size_t fr = 0, tot = 0;
+    budget = hipMemGetInfo(&fr, &tot) == hipSuccess ? fr / 4 : 0;
+  }
+  const bool keep = (size_t)a->every * 4 * n <= budget;
+  const int per_step = keep ? 5 : 1;
+  auto idx = [&](int64_t sl, int i) { return (size_t)sl * per_step + i; };
+  void *st[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (!keep)
+    for (int i = 1; i < 5; ++i) st[i] = alloc(n);
   std::vector<void *> seg;
-  for (int64_t i = 0; i < a->every; ++i) seg.push_back(alloc(n));
-  bool ok = lq && lr && res && zbuf && grad && st[1] && st[2] && st[3] && st[4];
+  for (int64_t i = 0; i < a->every * per_step; ++i) seg.push_back(alloc(n));
+  bool ok = lq && lr && res && zbuf && grad;
+  if (!keep) ok = ok && st[1] && st[2] && st[3] && st[4];
   for (void *p : seg) ok = ok && p;
   if (!ok) {
     release();
@@ -272,15 +289,19 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
     const int64_t c1 = std::min(c0 + a->every, a->nsteps);
     e = hipMemcpyAsync(seg[0], a->ckpt[ci], n, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) { rc = c->hipfail(e, "segment restore"); break; }
-    // recompute the step-start states of the segment
-    for (int64_t s = c0; s + 1 < c1 && rc == DGW_OK; ++s) {
+    // recompute the step-start states of the segment (and, when kept, the
+    // inner stage states; the last step's end state is not needed)
+    for (int64_t s = c0; s < c1 && rc == DGW_OK; ++s) {
+      const bool last = s + 1 == c1;
+      if (last && !keep) break;
       if ((e = launch_set_steps(a->d_aux, c->nshots, s, c->stream)) != hipSuccess) {
         rc = c->hipfail(e, "set_steps");
         break;
       }
-      const void *in = seg[s - c0];
-      for (int i = 0; i < 5 && rc == DGW_OK; ++i) {
-        void *out = (i == 4) ? seg[s - c0 + 1] : st[1 + (i & 1)];
+      const void *in = seg[idx(s - c0, 0)];
+      for (int i = 0; i < (last ? 4 : 5) && rc == DGW_OK; ++i) {
+        void *out = i == 4 ? seg[idx(s - c0 + 1, 0)]
+                           : keep ? seg[idx(s - c0, i + 1)] : st[1 + (i & 1)];
         rc = stage_explicit(c, in, out, res, i);
         in = out;
       }
@@ -296,22 +317,28 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
                           a->d_obs, a->nsteps, a->d_aux, c->d_len, c->dt, c->stream);
         if (e != hipSuccess) { rc = c->hipfail(e, "inject"); break; }
       }
-      // stage inputs of step s
-      st[0] = seg[s - c0];
-      for (int i = 0; i < 4 && rc == DGW_OK; ++i) rc = stage_explicit(c, st[i], st[i + 1], res, i);
+      // stage inputs of step s: kept, or recomputed from the step start
+      void *sx[5];
+      if (keep) {
+        for (int i = 0; i < 5; ++i) sx[i] = seg[idx(s - c0, i)];
+      } else {
+        sx[0] = seg[idx(s - c0, 0)];
+        for (int i = 1; i < 5; ++i) sx[i] = st[i];
+        for (int i = 0; i < 4 && rc == DGW_OK; ++i)
+          rc = stage_explicit(c, sx[i], sx[i + 1], res, i);
+      }
       for (int i = 4; i >= 0 && rc == DGW_OK; --i) {
         if (c->precision == 64) {
           AdjArgs<double> aa;
-          fill_adj(c, aa, st[i], lq, lr, zbuf, grad, i);
+          fill_adj(c, aa, sx[i], lq, lr, zbuf, grad, i);
           e = launch_adjoint_stage(c->R.N, 64, c->nshots, &aa, c->stream);
         } else {
           AdjArgs<float> aa;
-          fill_adj(c, aa, st[i], lq, lr, zbuf, grad, i);
+          fill_adj(c, aa, sx[i], lq, lr, zbuf, grad, i);
           e = launch_adjoint_stage(c->R.N, 32, c->nshots, &aa, c->stream);
         }
         if (e != hipSuccess) rc = c->hipfail(e, "adjoint stage launch");
       }
-      st[0] = nullptr;
     }
   }
   if (rc == DGW_OK) {
@@ -329,6 +356,13 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
   }
   release();
   return rc;
+}
+
+int dgw_set_adjoint_memory(dgw_ctx *c, int64_t bytes) {
+  if (!c) return DGW_EINVAL;
+  if (bytes < -1) return c->fail(DGW_EINVAL, "adjoint memory budget must be >= -1");
+  c->adj_budget = bytes;
+  return DGW_OK;
 }
 
 }  // extern "C"

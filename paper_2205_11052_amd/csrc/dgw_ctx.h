@@ -85,6 +85,9 @@ struct dgw_ctx {
   // differentiation state (adjoint.cpp)
   struct Adjoint;
   Adjoint *adj = nullptr;
+  // device bytes the reverse sweep may spend on kept stage states
+  // (-1: a quarter of the free device memory)
+  int64_t adj_budget = -1;
 
   int fail(int code, const std::string &msg);
   int hipfail(hipError_t e, const char *what);

@@ -349,6 +349,12 @@ class Solver:
         up = self._per_element(C, 21, "stiffness")
         self._check(self.lib.dgw_set_stiffness(self._ctx, _dptr(up)), "dgw_set_stiffness")
 
+    def set_adjoint_memory(self, nbytes=-1):
+        """Device bytes the reverse sweep may keep stage states in (-1:
+        a quarter of the free memory, 0: recompute them)."""
+        self._check(self.lib.dgw_set_adjoint_memory(self._ctx, int(nbytes)),
+                    "dgw_set_adjoint_memory")
+
     def set_flux(self, tau=1.0):
         """Upwind weight of the face flux (1 upwind, 0 central)."""
         self._check(self.lib.dgw_set_flux(self._ctx, float(tau)), "dgw_set_flux")

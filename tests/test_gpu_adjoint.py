@@ -252,3 +252,26 @@ def test_batched_gradients_of_uneven_lengths():
             % (i, lens[i], mis[i], J_o.item(), *errs))
         assert abs(mis[i] - J_o.item()) <= 1e-12 * J_o.item()
         assert max(errs) <= 1e-10
+
+
+def test_kept_stage_states_give_identical_gradients():
+    """The reverse sweep with the inner stage states kept (default budget)
+    and recomputed (budget 0) gives the same misfit and gradients bit for
+    bit, for a segment length that does not divide the step count."""
+    case = _small_case(3, nsteps=23, seed=11)
+    say("case adjoint memory budget")
+    out = []
+    for budget in (-1, 0):
+        s = _gpu(case, 64, 1)
+        s.set_adjoint_memory(budget)
+        s.zero_fields()
+        m = s.forward_checkpointed(case["nsteps"], 7, case["d_obs"][None])
+        out.append((m, s.adjoint()))
+        s.close()
+    (m1, g1), (m2, g2) = out
+    assert m1[0] == m2[0]
+    for a, b in zip(g1, g2):
+        assert np.array_equal(a, b)
+    s = _gpu(case, 64, 1)
+    with pytest.raises(Exception):
+        s.set_adjoint_memory(-2)
