@@ -275,3 +275,46 @@ def test_kept_stage_states_give_identical_gradients():
     s = _gpu(case, 64, 1)
     with pytest.raises(Exception):
         s.set_adjoint_memory(-2)
+
+
+def test_full_size_batched_gradients_equal_single_shots():
+    """The batched-gradient configuration at full size (82944 elements,
+    order 4, FP32, the autotuner's launch shape, checkpoints every 25
+    steps, zero observed data): two shots of different positions and
+    lengths (30 and 20 steps) in one batch give each shot's misfit and
+    gradient of its run alone, in the same launch shape, bit for bit.
+    Receivers sit at the two source points, so every trace is nonzero."""
+    w = W.build_workload("c1_layered_n24")
+    pos, _ = W.batched_shots()
+    lens = [30, 20]
+    rec = np.array([pos[0], pos[1]])
+    say("case full-size batched gradients K=%d" % w["K"])
+
+    def make(nshots, which, shape=None):
+        s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], 1.0, 32, nshots)
+        s.set_dt(s.suggest_dt(w["cfl"]))
+        for i, j in enumerate(which):
+            s.set_source(i, pos[j], w["f0"], 0.1, w["amp"], nsteps=lens[j])
+            s.set_receivers(i, rec, 30)
+        if shape is None:
+            shape = s.autotune()
+        else:
+            s.set_launch(*shape)
+        return s, shape
+
+    b, shape = make(2, [0, 1])
+    say("batched gradients launch shape %s" % (shape,))
+    b.zero_fields()
+    mis = b.forward_checkpointed(30, 25, np.zeros((2, 2, 3, 30)))
+    g = b.adjoint()
+    b.close()
+    for j in range(2):
+        s, _ = make(1, [j], shape)
+        s.zero_fields()
+        m1 = s.forward_checkpointed(30, 25, np.zeros((1, 2, 3, 30)))
+        g1 = s.adjoint()
+        s.close()
+        say("shot %d misfit batch %.6e alone %.6e" % (j, mis[j], m1[0]))
+        assert m1[0] == mis[j] and mis[j] > 0
+        for a, c in zip(g1, g):
+            assert np.array_equal(a[0], c[j])
