@@ -7,7 +7,12 @@
 * the reverse-mode gradient equals the complex-step derivative
   Im J(m + i h e_k) / h (h = 1e-30, no subtractive cancellation) for every
   parameter of a small mesh, equals central finite differences, and does not
-  depend on the checkpoint interval.
+  depend on the checkpoint interval;
+* dot-product test: the reverse-mode transpose of the right-hand side (the
+  map the adjoint is built from) satisfies <a, L b> = <L^T a, b> for random
+  a, b, with L b from the forward right-hand side and L^T a from one
+  vector-Jacobian product, and L^T a equals the transpose of the assembled
+  matrix applied to a.
 """
 
 import math
@@ -18,7 +23,7 @@ import torch
 
 import workloads as W
 from oracle import adjoint, solver
-from oracle_helpers import random_medium, tensors
+from oracle_helpers import assemble_L, random_medium, tensors
 
 
 def test_ricker_closed_form():
@@ -123,3 +128,26 @@ def test_gradient_matches_central_differences_and_checkpointing():
             vals.append(_misfit(P, p, q0, dt, nsteps, d_obs).item())
         fd = (vals[0] - vals[1]) / (2 * delta)
         assert abs(fd - g[k].item()) < 1e-6 * abs(fd)
+
+
+def test_dot_product_transpose_of_rhs():
+    for periodic, n, N in ((True, 3, 2), (False, 2, 1), (False, 1, 3)):
+        mesh = W.kuhn_cube(n, 1.0, periodic=periodic)
+        P = solver.Problem(mesh, N)
+        rho, lam, mu = tensors(*random_medium(P.K, 13 + N))
+        rng = np.random.default_rng(21 + N)
+        a = torch.as_tensor(rng.standard_normal((P.K, 9, P.Np)))
+        b = torch.as_tensor(rng.standard_normal((P.K, 9, P.Np)))
+        Lb = solver.rhs(P, b, rho, lam, mu)
+        x = torch.zeros_like(b).requires_grad_(True)
+        (LTa,) = torch.autograd.grad(solver.rhs(P, x, rho, lam, mu), x,
+                                     grad_outputs=a)
+        lhs, rhs_ = torch.sum(a * Lb).item(), torch.sum(LTa * b).item()
+        scale = torch.linalg.norm(a).item() * torch.linalg.norm(Lb).item()
+        assert abs(lhs - rhs_) <= 1e-13 * scale
+        if periodic:
+            continue                      # assembled L too large here
+        L = assemble_L(P, rho, lam, mu)
+        want = L.T @ a.reshape(-1).numpy()
+        assert np.abs(LTa.reshape(-1).numpy() - want).max() \
+            <= 1e-13 * np.abs(want).max()
