@@ -211,6 +211,17 @@ int dgw_forward_checkpointed(dgw_ctx *ctx, int64_t nsteps, int64_t ckpt_every,
                              const double *d_obs, double *misfit);
 int dgw_adjoint(dgw_ctx *ctx, double *g_rho, double *g_lam, double *g_mu);
 
+/* State generation: a counter the context bumps on every call that changes
+ * what a run computes (dgw_set_material, dgw_set_dt, dgw_set_source,
+ * dgw_set_receivers, dgw_set_fields, dgw_set_damping, dgw_set_flux,
+ * dgw_set_stiffness, and dgw_step when it advances a shot).
+ * dgw_forward_checkpointed records the value it ends at, and dgw_adjoint
+ * returns DGW_ESTATE when the counter has moved since, because the reverse
+ * sweep reads the traces, material, time step and tables of the live
+ * context.  Callers that keep several forwards apart compare the value
+ * themselves.  *gen receives the current value. */
+int dgw_state_generation(const dgw_ctx *ctx, uint64_t *gen);
+
 /* Device memory the reverse sweep of dgw_adjoint may spend on keeping the
  * inner stage states of a checkpoint segment (ckpt_every x 4 states of all
  * shots): within the budget, the states the segment's recomputation

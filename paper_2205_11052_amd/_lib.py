@@ -46,6 +46,7 @@ SIGNATURES = {
                                      C.POINTER(C.c_int32), C.c_int, _PI64]),
     "dgw_forward_checkpointed": (C.c_int, [_P, _I64, _I64, _D, _D]),
     "dgw_adjoint": (C.c_int, [_P, _D, _D, _D]),
+    "dgw_state_generation": (C.c_int, [_P, C.POINTER(C.c_uint64)]),
     "dgw_autotune": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "dgw_set_launch": (C.c_int, [_P, C.c_int, C.c_int, C.c_int]),

@@ -22,6 +22,7 @@ using namespace dgw;
 
 struct dgw_ctx::Adjoint {
   bool ready = false;
+  uint64_t gen = 0;             // context generation the forward ended at
   int64_t nsteps = 0, every = 0;
   std::vector<void *> ckpt;     // per checkpoint: [S][K][9][Np]
   double *d_obs = nullptr;      // [S][rmax][3][nsteps]
@@ -215,6 +216,7 @@ int dgw_forward_checkpointed(dgw_ctx *c, int64_t nsteps, int64_t every,
     }
     misfit[s] = J;
   }
+  a->gen = c->gen;
   a->ready = true;
   return DGW_OK;
 }
@@ -223,6 +225,10 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
   if (!c) return DGW_EINVAL;
   if (!c->adj || !c->adj->ready)
     return c->fail(DGW_ESTATE, "call dgw_forward_checkpointed first");
+  if (c->adj->gen != c->gen)
+    return c->fail(DGW_ESTATE, "the solver state changed after dgw_forward_checkpointed "
+                               "(a setter, dgw_set_fields or dgw_step ran in between): "
+                               "run the checkpointed forward again");
   if (c->flux_tau != 1.0)
     return c->fail(DGW_ESTATE, "the adjoint supports the upwind flux only (flux weight 1)");
   if (c->have_aniso)

@@ -268,6 +268,7 @@ extern "C" int dgw_set_stiffness(dgw_ctx *c, const double *C) {
   if (!c->have_mesh || !c->have_mat)
     return c->fail(DGW_ESTATE, "set the mesh and the material first");
   c->invalidate_graph();
+  c->touch();
   if (!C) {
     c->have_aniso = false;
     c->aniso_C.clear();

@@ -526,6 +526,7 @@ int dgw_set_material(dgw_ctx *c, const double *rho, const double *lam,
   int rc = c->material_meta();
   if (rc) return rc;
   c->have_mat = true;
+  c->touch();
   // the impedance matrices of anisotropic elements depend on rho
   if (c->have_aniso && (rc = c->aniso_table())) return rc;
   return DGW_OK;
@@ -554,6 +555,7 @@ int dgw_set_dt(dgw_ctx *c, double dt) {
   if (!(dt > 0) || !std::isfinite(dt)) return c->fail(DGW_EINVAL, "dt must be positive");
   c->dt = dt;
   c->have_dt = true;
+  c->touch();
   c->invalidate_graph();
   return DGW_OK;
 }
@@ -586,6 +588,7 @@ int dgw_set_source(dgw_ctx *c, int shot, const double *xyz, const double *moment
   c->h_src_par[(size_t)shot * 10 + 8] = amp;
   c->h_src_elem[shot] = (int32_t)k;
   c->h_len[shot] = nsteps > 0 ? nsteps : std::numeric_limits<int64_t>::max();
+  c->touch();
   return c->sync_shot_tables();
 }
 
@@ -616,6 +619,7 @@ int dgw_set_receivers(dgw_ctx *c, int shot, int nrec, const double *xyz,
       c->h_rec_w[((size_t)shot * c->rmax + r) * Np + j] = r < nrec ? w[(size_t)r * Np + j] : 0.0;
   }
   c->h_nrec[shot] = nrec;
+  c->touch();
   c->h_cap_shot.resize(c->nshots, 0);
   c->h_cap_shot[shot] = max_samples;
   const size_t off = (size_t)shot * c->rmax;
@@ -630,6 +634,7 @@ int dgw_set_fields(dgw_ctx *c, int shot, const double *q) {
   if (!c->have_mesh) return c->fail(DGW_ESTATE, "set the mesh first");
   if (shot < 0 || shot >= c->nshots) return c->fail(DGW_ERANGE, "shot out of range");
   if (!q) return c->fail(DGW_EINVAL, "null field array");
+  c->touch();
   const size_t n = (size_t)c->mesh.K * 9 * c->R.Np;
   int rc;
   if (c->precision == 64) {
@@ -678,6 +683,7 @@ int dgw_step(dgw_ctx *c, int64_t nsteps) {
     longest = std::max(longest, adv[s]);
   }
   if (longest == 0) return DGW_OK;
+  c->touch();
   int rc;
   if ((rc = c->gather_shots_to_cur(adv))) return rc;
   const int cur0 = c->cur;
@@ -839,6 +845,7 @@ int dgw_set_damping(dgw_ctx *c, const double *sigma) {
   if (!c) return DGW_EINVAL;
   if (!c->have_mesh) return c->fail(DGW_ESTATE, "set the mesh first");
   c->invalidate_graph();
+  c->touch();
   if (!sigma) {
     c->have_sponge = false;
     return DGW_OK;
@@ -864,6 +871,7 @@ int dgw_set_flux(dgw_ctx *c, double tau) {
     return c->fail(DGW_EINVAL, "flux weight must lie in [0, 1]");
   c->flux_tau = tau;
   c->invalidate_graph();
+  c->touch();
   return DGW_OK;
 }
 
@@ -877,6 +885,12 @@ int dgw_stage_kernel_ms(dgw_ctx *c, double *ms, int64_t *launches) {
   if (!c || !ms) return DGW_EINVAL;
   *ms = c->timed_ms;
   if (launches) *launches = c->timed_launches;
+  return DGW_OK;
+}
+
+int dgw_state_generation(const dgw_ctx *c, uint64_t *gen) {
+  if (!c || !gen) return DGW_EINVAL;
+  *gen = c->gen;
   return DGW_OK;
 }
 

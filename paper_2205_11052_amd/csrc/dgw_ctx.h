@@ -76,6 +76,12 @@ struct dgw_ctx {
   bool graph_ok = false;
   int graph_from = 0;
 
+  // Bumped by every call that changes what a run computes (setters,
+  // dgw_set_fields, dgw_step); the checkpointed forward records it and the
+  // reverse sweep refuses to run when it has moved.
+  uint64_t gen = 0;
+  void touch() { ++gen; }
+
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   int ev_pool_used = 0;

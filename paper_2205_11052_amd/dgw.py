@@ -302,6 +302,13 @@ class Solver:
             "dgw_forward_checkpointed")
         return mis
 
+    def generation(self):
+        """The context's state generation (see dgw_state_generation)."""
+        g = C.c_uint64()
+        self._check(self.lib.dgw_state_generation(self._ctx, C.byref(g)),
+                    "dgw_state_generation")
+        return g.value
+
     def adjoint(self):
         g = [np.empty((self.nshots, self.K)) for _ in range(3)]
         self._check(self.lib.dgw_adjoint(self._ctx, _dptr(g[0]), _dptr(g[1]),
@@ -387,11 +394,17 @@ if torch is not None:
             solver.zero_fields()
             mis = solver.forward_checkpointed(nsteps, ckpt_every, d_obs)
             ctx.solver = solver
+            ctx.generation = solver.generation()
             ctx.device = rho.device
             return torch.as_tensor(mis, dtype=torch.float64, device=rho.device)
 
         @staticmethod
         def backward(ctx, grad_out):
+            if ctx.solver.generation() != ctx.generation:
+                raise RuntimeError(
+                    "ElasticMisfit.backward: the solver ran or changed after this "
+                    "forward (another apply, a setter or a step); its checkpoints "
+                    "belong to a different forward")
             g = ctx.solver.adjoint()
             w = grad_out.detach().to("cpu", torch.float64).numpy()
             outs = [torch.as_tensor((w[:, None] * gi).sum(axis=0),

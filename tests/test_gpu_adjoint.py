@@ -117,6 +117,40 @@ def test_autograd_function_and_batched_shots():
             assert np.array_equal(a[0], b[i])
 
 
+def test_stale_forward_is_refused():
+    """The reverse sweep reads the live context: any setter, field upload or
+    step after the checkpointed forward makes dgw_adjoint refuse (status
+    ESTATE), and ElasticMisfit.backward refuses a forward that a later apply
+    replaced."""
+    from paper_2205_11052_amd import DGWError
+    case = _small_case(2, nsteps=12, seed=3)
+    say("case stale adjoint state")
+    s = _gpu(case, 64)
+    changes = [lambda: s.set_material(*case["start"]), lambda: s.zero_fields(),
+               lambda: s.step(1), lambda: s.set_dt(case["dt"]),
+               lambda: s.set_receivers(0, case["rec"], case["nsteps"])]
+    for change in changes:
+        s.zero_fields()
+        s.forward_checkpointed(case["nsteps"], 4, case["d_obs"][None])
+        change()
+        with pytest.raises(DGWError) as err:
+            s.adjoint()
+        assert err.value.status == "DGW_ESTATE"
+    s.zero_fields()
+    s.forward_checkpointed(case["nsteps"], 4, case["d_obs"][None])
+    g = s.adjoint()
+    assert all(np.isfinite(x).all() for x in g)
+    # two forwards through the autograd wrapper: only the last can go back
+    rho, lam, mu = (torch.tensor(a, requires_grad=True) for a in case["start"])
+    m1 = ElasticMisfit.apply(rho, lam, mu, s, case["d_obs"][None], case["nsteps"], 4)
+    m2 = ElasticMisfit.apply(rho, lam, mu, s, 0.5 * case["d_obs"][None],
+                             case["nsteps"], 4)
+    with pytest.raises(RuntimeError):
+        m1.sum().backward(retain_graph=True)
+    m2.sum().backward()
+    assert torch.isfinite(rho.grad).all()
+
+
 def _c3_reduced(n=4, nsteps=300):
     """Layered true medium, blob-perturbed start, 64 surface receivers."""
     wt = W.build_workload("c3_adjoint", n=n)
