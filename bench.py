@@ -11,9 +11,15 @@ events.
 
 Metric: GDOF-stage/s = 9 * Np * K * 5 * steps / seconds / 1e9.
 
+Timing: W warm-up steps, then one graph's worth of steps (so the captured
+graph is built and replayed once before any window), then 5 windows of K
+steps; the median window gives `value` and `ms_per_step`.
+
 Extra forms reported beside the headline (same GPU, same mesh and medium):
-FP32 fields and arithmetic (error against the FP64 run stated), a batch of 32
-FP32 shots advanced together, and order 6 in FP64 and FP32.  The adjoint form
+FP32 fields and arithmetic, a batch of 32 FP32 shots advanced together, and
+order 6 in FP64 and FP32.  The FP32 error against the FP64 run is stated on
+the receiver traces and the final fields after the full 2000 steps from
+zero fields.  The adjoint form
 reports seconds per shot of the misfit gradient on the 24576-element order-3
 workload, with its error against central differences measured in the run.
 
@@ -24,8 +30,12 @@ library's stream, against 8 TB/s.  "traffic" is the HBM bytes per launch the
 hardware counters measured for this kernel source and launch shape (null
 when either differs).
 
-CPU baseline: the CPU oracle (plain PyTorch FP64) timed on the host on a
-bounded sample of the same workload (three LSERK4 steps of the full mesh).
+The roofline also states the algorithmic FLOP rate (minimal operation
+count per element, `stage_flops`) against the FP64 peak of 78.6 TFLOP/s.
+
+CPU baseline: the CPU oracle (plain PyTorch FP64) on one pinned host core,
+timed on a bounded sample of the same workload (one LSERK4 step of the full
+mesh), with the CPU model and the host's core count.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                        [--no-forms] [--no-adjoint] [--shape K,E,W]
@@ -61,16 +71,82 @@ MEASURED_TRAFFIC = {
 
 
 def measured_traffic(shape):
+    m = MEASURED_TRAFFIC
+    if kernel_source_sha() != m["kernel_source_sha256"] or tuple(shape) != m["launch_shape"]:
+        return None
+    return m["bytes_per_launch"]
+
+
+# Matrix-pipe and vector-ALU busy fractions of the same kernel, from
+# rocprofv3 counters (SQ_VALU_MFMA_BUSY_CYCLES and SQ_ACTIVE_INST_VALU over
+# SQ_BUSY_CYCLES x SIMDs), reported under the same source-hash and
+# launch-shape condition as the traffic.
+MEASURED_COUNTERS = {
+    "kernel_source_sha256": MEASURED_TRAFFIC["kernel_source_sha256"],
+    "launch_shape": MEASURED_TRAFFIC["launch_shape"],
+    "values": {"mfma_busy": 0.441, "valu_busy": 0.208, "wave_wait_frac": 0.279},
+}
+
+
+def kernel_source_sha():
     import hashlib
     h = hashlib.sha256()
     for name in ("stage.hip", "dgw_internal.h"):
         with open(os.path.join(ROOT, "paper_2205_11052_amd", "csrc", name), "rb") as f:
             h.update(f.read())
-    sha = h.hexdigest()
-    m = MEASURED_TRAFFIC
-    if sha != m["kernel_source_sha256"] or tuple(shape) != m["launch_shape"]:
+    return h.hexdigest()
+
+
+def measured_counters(shape):
+    m = MEASURED_COUNTERS
+    if kernel_source_sha() != m["kernel_source_sha256"] or tuple(shape) != m["launch_shape"]:
         return None
-    return m["bytes_per_launch"]
+    return dict(m["values"])
+
+
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+FULL_STEPS = 2000      # the full run length of the order-4 and order-6 workloads
+
+
+def stage_flops(K, N, nshots=1):
+    """Algorithmic floating-point operations of one stage launch, minimal
+    form per element: 18 reference matrix-vector products (9 for the stress
+    divergence, 9 for the velocity gradient), 6 lifted components per face,
+    about 150 operations per face node for the Riemann solve, and the RK
+    update (2 operations per value per register)."""
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    Nfp = (N + 1) * (N + 2) // 2
+    per = 2 * 18 * Np * Np + 2 * 6 * 4 * Np * Nfp + 150 * 4 * Nfp + 4 * 9 * Np
+    return nshots * K * per
+
+
+def full_length_run(s, nsteps):
+    """Run shot 0 from zero fields for nsteps steps; traces and final fields."""
+    s.zero_fields()
+    s.step(nsteps)
+    return {"traces": s.read_traces(0), "fields": s.get_fields(0), "steps": nsteps}
+
+
+def full_length_errors(a, b):
+    """Errors of run a against run b (traces over all receivers, components
+    and samples; final fields over all nodal values)."""
+    ta, tb = np.asarray(a["traces"]), np.asarray(b["traces"])
+    fa, fb = np.asarray(a["fields"]), np.asarray(b["fields"])
+    peak = np.abs(tb).max(axis=(1, 2))
+    live = peak >= 1e-3 * peak.max()
+    per_rec = [float(np.linalg.norm(ta[r] - tb[r]) / np.linalg.norm(tb[r]))
+               for r in np.nonzero(live)[0]]
+    return {"steps": b["steps"],
+            "traces_rel_l2": rel_l2(ta, tb),
+            "traces_worst_receiver_rel_l2": max(per_rec),
+            "receivers_compared": len(per_rec),
+            "fields_rel_l2": rel_l2(fa, fb),
+            "fields_per_component_rel_l2": [rel_l2(fa[:, c], fb[:, c]) for c in range(9)],
+            "fields_max_abs_err_over_max": float(np.abs(fa - fb).max() / np.abs(fb).max()),
+            "note": "both runs from zero fields with the source active, same dt; "
+                    "per-receiver error over receivers whose peak is >= 1e-3 of "
+                    "the largest"}
 
 
 def stage_bytes(K, Np, real_bytes, nshots=1):
@@ -113,18 +189,29 @@ def copy_probe(torch, nbytes=1 << 30, reps=3):
           flush=True)
 
 
-def timed_steps(torch, s, stream, steps, warmup):
+GRAPH_STEPS = 10      # steps per captured HIP graph in the library
+REPEATS = 5           # timed windows; the median is reported
+
+
+def timed_steps(torch, s, stream, steps, warmup, repeats=REPEATS):
+    """Seconds for `steps` steps: the median of `repeats` windows, each timed
+    with events on the solver's stream.  Before timing, `warmup` steps run
+    and then one more graph's worth of steps, so the graph the timed windows
+    replay is already captured, instantiated and replayed once (its capture
+    is never inside a window).  Returns (median seconds, all window seconds)."""
     s.step(warmup)
+    s.step(GRAPH_STEPS)
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    t0.record(stream)
-    s.step(steps)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    return t0.elapsed_time(t1) / 1000.0, wall
+    times = []
+    for _ in range(repeats):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        s.step(steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        times.append(t0.elapsed_time(t1) / 1000.0)
+    return float(np.median(times)), times
 
 
 def kernel_avg_ms(s, steps=10):
@@ -216,6 +303,7 @@ def adjoint_form(torch, stream, nsteps=1500, ckpt=100, n_fd=2):
         s64.close()
     res["fd_max_rel_error_fp64"] = worst
     res["fd_entries"] = nfd
+    res["kernels"] = adjoint_kernel_times(torch, stream, make, ws, dt, d)
     res["fp32_grad_rel_l2_vs_fp64"] = rel_l2(np.concatenate(grads[32]),
                                              np.concatenate(grads[64]))
     res["workload"] = ("c3_adjoint: 6*16^3 = 24576 tetrahedra, order 3, %d steps, "
@@ -223,32 +311,73 @@ def adjoint_form(torch, stream, nsteps=1500, ckpt=100, n_fd=2):
     return res
 
 
-def order6_form(torch, stream, w, steps, warmup):
+def reverse_stage_bytes(K, Np, real_bytes):
+    """Algorithmic HBM bytes of one reverse (adjoint) stage: the stage input
+    q read, the adjoint states lam_q and lam_r read and written, the
+    per-element data and connectivity read, the FP64 gradient (3 values per
+    element) read and written."""
+    return K * (5 * 9 * Np * real_bytes + META_BYTES + 2 * 3 * 8)
+
+
+def adjoint_kernel_times(torch, stream, make, ws, dt, d, nsteps=100):
+    """Average duration of one reverse stage (its two launches) and of one
+    forward stage launch, timed with HIP events on the library's stream in a
+    short checkpointed run (timing on; the timed seconds per shot above are
+    measured with timing off), and the reverse stage's HBM roofline."""
+    out = {}
+    K, N = ws["K"], ws["N"]
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    with torch.cuda.stream(stream):
+        for prec in (64, 32):
+            s = make(prec, ws, dt)
+            s.enable_timing(True)
+            s.zero_fields()
+            s.forward_checkpointed(nsteps, 20, d[..., :nsteps])
+            fms, _ = s.stage_kernel_ms()
+            s.adjoint()
+            rms, nrev = s.adjoint_stage_ms()
+            s.close()
+            b = reverse_stage_bytes(K, Np, prec // 8)
+            out["fp%d" % prec] = {
+                "forward_stage_ms": round(fms, 5), "reverse_stage_ms": round(rms, 5),
+                "reverse_over_forward": round(rms / fms, 3),
+                "reverse_stages_timed": nrev,
+                "reverse_bytes_per_stage": b,
+                "reverse_hbm_frac": round(b / (rms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "forward_hbm_frac": round(stage_bytes(K, Np, prec // 8) / (fms / 1e3) / 1e9
+                                          / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def order6_form(torch, stream, w, steps, warmup, full_steps=FULL_STEPS):
     """FP32 and FP64 at order 6 (84 nodes) on the same mesh and medium:
-    throughput, and the FP32 fields' error against the FP64 ones after the
-    same steps."""
+    throughput, and the FP32 run's error against the FP64 run on the
+    receiver traces and final fields after the full run from zero fields
+    (dt from the CFL formula at order 6)."""
     import workloads as W
     w6 = W.build_workload("c1_layered_n24", N=6)
     out = {}
-    fields = {}
+    runs = {}
     for prec in (64, 32):
         with torch.cuda.stream(stream):
             s = build_solver(w6, prec, stream=stream.cuda_stream)
             sec, _ = timed_steps(torch, s, stream, steps, warmup)
             kms, _ = kernel_avg_ms(s)
-            fields[prec] = s.get_fields(0)
+            runs[prec] = full_length_run(s, full_steps)
             shape = s.shape
             s.close()
         Np = 84
+        peak = FP64_PEAK_TFLOPS if prec == 64 else FP32_PEAK_TFLOPS
         out["fp%d" % prec] = {
             "value": round(9 * Np * w6["K"] * 5 * steps / sec / 1e9, 3),
             "ms_per_step": round(sec / steps * 1e3, 4),
             "kernel_avg_ms": round(kms, 5),
             "hbm_frac": round(stage_bytes(w6["K"], Np, prec // 8) / (kms / 1e3) / 1e9
                               / HBM_PEAK_GBS, 4),
+            "flops_frac": round(stage_flops(w6["K"], 6) / (kms / 1e3) / 1e12 / peak, 4),
             "launch_shape": list(shape)}
     out["fp32"]["speedup_vs_fp64"] = round(out["fp32"]["value"] / out["fp64"]["value"], 3)
-    out["fp32"]["fields_rel_l2_vs_fp64"] = rel_l2(fields[32], fields[64])
+    out["fp32"]["error_vs_fp64"] = full_length_errors(runs[32], runs[64])
     return out
 
 
@@ -423,25 +552,54 @@ def fwi_form(torch, stream, nsteps=600, iterations=3, prec=32):
             "misfit_ratio": round(f[-1] / f[0], 4)}
 
 
-def cpu_baseline(w, steps=3):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, steps=1):
+    """The oracle (plain PyTorch FP64, never tuned for speed) on ONE host
+    core: torch intra-op threads set to 1 and the process pinned to one
+    core in-process for the measurement (both restored afterwards).  Sample:
+    one warm-up right-hand side, then `steps` full LSERK4 steps (5 stages
+    each) of the full 82944-element order-4 workload from zero fields."""
     import torch
     from oracle import solver as O
-    P = O.Problem(w["mesh"], w["N"])
-    t = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64))
-    P.set_source(w["source"], w["f0"], w["t0"], w["amp"])
-    q = torch.zeros(w["K"], 9, P.Np, dtype=torch.float64)
-    dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
-    rho, lam, mu = t(w["rho"]), t(w["lam"]), t(w["mu"])
-    O.lserk_step(P, q, 0.0, dt, rho, lam, mu)       # warm-up
-    t0 = time.perf_counter()
-    for s_ in range(steps):
-        q = O.lserk_step(P, q, s_ * dt, dt, rho, lam, mu)
-    sec = time.perf_counter() - t0
+    threads = torch.get_num_threads()
+    affinity = os.sched_getaffinity(0)
+    core = min(affinity)
+    torch.set_num_threads(1)
+    os.sched_setaffinity(0, {core})
+    try:
+        P = O.Problem(w["mesh"], w["N"])
+        t = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64))
+        P.set_source(w["source"], w["f0"], w["t0"], w["amp"])
+        q = torch.zeros(w["K"], 9, P.Np, dtype=torch.float64)
+        dt = P.suggest_dt(w["rho"], w["lam"], w["mu"], w["cfl"])
+        rho, lam, mu = t(w["rho"]), t(w["lam"]), t(w["mu"])
+        O.rhs(P, q, rho, lam, mu)                      # warm-up
+        t0 = time.perf_counter()
+        for s_ in range(steps):
+            q = O.lserk_step(P, q, s_ * dt, dt, rho, lam, mu)
+        sec = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(threads)
+        os.sched_setaffinity(0, affinity)
     dof = 9 * P.Np * w["K"]
     return {"value": dof * 5 * steps / sec / 1e9, "unit": "GDOF-stage/s",
-            "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": "%d LSERK4 steps (%d stages) of the full 82944-element "
-                      "order-4 FP64 workload, %.2f s" % (steps, 5 * steps, sec)}
+            "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "cores_available": len(affinity), "pinned_core": core,
+            "torch_threads": 1,
+            "sample": "%d LSERK4 step(s) (%d stages) of the full 82944-element "
+                      "order-4 FP64 workload on one pinned core, %.2f s"
+                      % (steps, 5 * steps, sec)}
 
 
 def main():
@@ -479,23 +637,32 @@ def main():
 
     with torch.cuda.stream(stream):
         s = build_solver(w, 64, stream=stream.cuda_stream, shape=shape)
-        sec, wall = timed_steps(torch, s, stream, args.steps, args.warmup)
+        sec, windows = timed_steps(torch, s, stream, args.steps, args.warmup)
         kms, nl = kernel_avg_ms(s)
         s.check_finite()
         shape64 = s.shape
-        q64 = s.get_fields(0) if not args.no_forms else None
+        full64 = None if args.no_forms else full_length_run(s, FULL_STEPS)
+    del s
     value = dof * 5 * args.steps / sec / 1e9
     bytes_launch = stage_bytes(K, Np, 8)
     achieved = bytes_launch / (kms / 1e3) / 1e9
+    flops = stage_flops(K, N)
+    ms_step = sec / args.steps * 1e3
     out = {
         "metric": "GDOF-stage/s", "value": round(value, 3),
         "unit": "GDOF-stage/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(sec / args.steps * 1e3, 4),
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "c1_layered_n24", "elements": K, "order": N,
                    "nodes_per_element": Np, "dof": dof, "shots": 1,
                    "stages_per_step": 5, "parallelism": "none (1 GPU)"},
+        "timing": {"windows": len(windows), "statistic": "median",
+                   "window_ms_per_step": [round(t / args.steps * 1e3, 4)
+                                          for t in windows],
+                   "graph_warmup_steps": GRAPH_STEPS,
+                   "five_stage_kernels_ms": round(5 * kms, 4),
+                   "step_over_kernels": round(ms_step / (5 * kms), 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -504,11 +671,15 @@ def main():
                      "kernel_avg_ms": round(kms, 5),
                      "launches_timed": nl,
                      "bytes_per_launch": bytes_launch,
+                     "flops_per_launch": flops,
+                     "flops_achieved_tflops": round(flops / (kms / 1e3) / 1e12, 3),
+                     "flops_peak_tflops": FP64_PEAK_TFLOPS,
+                     "flops_frac": round(flops / (kms / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+                     "counters": measured_counters(shape64),
                      "launch_shape": {"kernel": shape64[0],
                                       "elements_per_workgroup": shape64[1],
                                       "persistent_wgs_per_cu": shape64[2]}},
     }
-    del s
     if not args.no_forms:
         forms = {}
         with torch.cuda.stream(stream):
@@ -516,7 +687,7 @@ def main():
             sec32, _ = timed_steps(torch, s32, stream, args.steps, args.warmup)
             k32, _ = kernel_avg_ms(s32)
             shape32 = s32.shape
-            err32 = rel_l2(s32.get_fields(0), q64)
+            full32 = full_length_run(s32, FULL_STEPS)
         del s32
         forms["fp32"] = {
             "value": round(dof * 5 * args.steps / sec32 / 1e9, 3),
@@ -525,10 +696,10 @@ def main():
             "kernel_avg_ms": round(k32, 5),
             "hbm_frac": round(stage_bytes(K, Np, 4) / (k32 / 1e3) / 1e9
                               / HBM_PEAK_GBS, 4),
+            "flops_frac": round(flops / (k32 / 1e3) / 1e12 / FP32_PEAK_TFLOPS, 4),
             "launch_shape": list(shape32),
-            "fields_rel_l2_vs_fp64": err32,
-            "error_note": "final fields after the same %d steps from zero, "
-                          "source active" % (args.warmup + args.steps + 10)}
+            "error_vs_fp64": full_length_errors(full32, full64)}
+        del full64, full32
         pos, lens = W.batched_shots()
         nb = len(pos)
         bsteps = max(10, args.steps // 10)

@@ -161,6 +161,7 @@ int dgw_shot_steps(dgw_ctx *ctx, int shot, int64_t *steps);
  * the stress term), accumulated in FP64 on the device. */
 int dgw_energy(dgw_ctx *ctx, int shot, double *E);
 
+
 /* DGW_ENONFINITE if any field value of any shot is NaN or infinite. */
 int dgw_check_finite(dgw_ctx *ctx);
 
@@ -295,6 +296,12 @@ int dgw_set_launch(dgw_ctx *ctx, int kernel, int elems_per_block, int wgs_per_cu
  * (0 if none was timed); enable with dgw_enable_timing(ctx, 1). */
 int dgw_enable_timing(dgw_ctx *ctx, int on);
 int dgw_stage_kernel_ms(dgw_ctx *ctx, double *ms, int64_t *launches);
+
+/* Average duration in milliseconds of one reverse (adjoint) stage -- its two
+ * kernel launches -- over the first (at most 200) reverse stages of the last
+ * dgw_adjoint call made with timing enabled, from HIP events on the
+ * context's stream; *stages receives how many were timed (0: none). */
+int dgw_adjoint_stage_ms(dgw_ctx *ctx, double *ms, int64_t *stages);
 
 /* Sizes: Np = (N+1)(N+2)(N+3)/6 and Nfp = (N+1)(N+2)/2 of the context. */
 int dgw_sizes(const dgw_ctx *ctx, int *Np, int *Nfp, int64_t *K);

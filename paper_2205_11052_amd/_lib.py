@@ -56,6 +56,7 @@ SIGNATURES = {
     "dgw_set_adjoint_memory": (C.c_int, [_P, _I64]),
     "dgw_enable_timing": (C.c_int, [_P, C.c_int]),
     "dgw_stage_kernel_ms": (C.c_int, [_P, _D, _PI64]),
+    "dgw_adjoint_stage_ms": (C.c_int, [_P, _D, _PI64]),
     "dgw_sizes": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), _PI64]),
 }
 

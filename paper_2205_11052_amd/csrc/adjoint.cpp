@@ -290,6 +290,15 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
   }
   const int64_t nck = (int64_t)a->ckpt.size();
   const int64_t stride = K * 9 * Np;
+  // timing: event pairs around the first kAdjTimed reverse stages
+  constexpr int kAdjTimed = 200;
+  int timed_used = 0;
+  if (c->timing)
+    while ((int)c->adj_ev.size() < 2 * kAdjTimed) {
+      hipEvent_t ev;
+      if (hipEventCreate(&ev) != hipSuccess) break;
+      c->adj_ev.push_back(ev);
+    }
   for (int64_t ci = nck - 1; ci >= 0 && rc == DGW_OK; --ci) {
     const int64_t c0 = ci * a->every;
     const int64_t c1 = std::min(c0 + a->every, a->nsteps);
@@ -334,6 +343,8 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
           rc = stage_explicit(c, sx[i], sx[i + 1], res, i);
       }
       for (int i = 4; i >= 0 && rc == DGW_OK; --i) {
+        const bool tm = c->timing && timed_used + 2 <= (int)c->adj_ev.size();
+        if (tm) (void)hipEventRecord(c->adj_ev[timed_used], c->stream);
         if (c->precision == 64) {
           AdjArgs<double> aa;
           fill_adj(c, aa, sx[i], lq, lr, zbuf, grad, i);
@@ -344,12 +355,26 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
           e = launch_adjoint_stage(c->R.N, 32, c->nshots, &aa, c->stream);
         }
         if (e != hipSuccess) rc = c->hipfail(e, "adjoint stage launch");
+        if (tm) {
+          (void)hipEventRecord(c->adj_ev[timed_used + 1], c->stream);
+          timed_used += 2;
+        }
       }
     }
   }
   if (rc == DGW_OK) {
     std::vector<double> g((size_t)c->nshots * K * 3);
     rc = c->download(g.data(), grad, sizeof(double) * g.size());
+    if (rc == DGW_OK && c->timing) {
+      double tot = 0;
+      for (int i = 0; i + 1 < timed_used; i += 2) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, c->adj_ev[i], c->adj_ev[i + 1]);
+        tot += ms;
+      }
+      c->adj_timed = timed_used / 2;
+      c->adj_ms = c->adj_timed ? tot / c->adj_timed : 0.0;
+    }
     if (rc == DGW_OK)
       for (int s = 0; s < c->nshots; ++s)
         for (int64_t k = 0; k < K; ++k) {

@@ -288,5 +288,11 @@ extern "C" int dgw_set_stiffness(dgw_ctx *c, const double *C) {
     return rc;
   }
   c->have_aniso = true;
+  // the minimal-form kernel is isotropic only: back to the default shape
+  if (c->kernel == 2) {
+    c->kernel = 0;
+    c->block = default_block(0, c->R.N, c->precision);
+    c->wpc = 0;
+  }
   return DGW_OK;
 }

@@ -80,6 +80,7 @@ int dgw_ctx::ensure_device() {
   hipError_t e = hipGetDeviceCount(&n);
   if (e != hipSuccess || n <= 0) return fail(DGW_EHIP, "no HIP device available");
   int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess) device = dev;
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
       cus > 0)
@@ -181,16 +182,36 @@ int dgw_ctx::upload_operators() {
           const int i = 16 * mt + l % 16, m = 4 * ks + l / 16;
           if (i < Np) al[((size_t)ks * MT + mt) * 64 + l] = R.LIFT[(size_t)i * NF + m];
         }
+    // per-face lift fragments of the minimal-form kernel, scaled by the
+    // face's reference coefficient (2 for face 0, -2 for faces 1-3; powers
+    // of two, so the scaling is exact): Alf[f][ks][mt][l] =
+    // c_f LIFT[16 mt + l % 16][f Nfp + 4 ks + l / 16], zero past Nfp
+    const int Nfp = R.Nfp, KF = (Nfp + 3) / 4;
+    std::vector<double> af((size_t)4 * KF * MT * 64, 0.0);
+    for (int f = 0; f < 4; ++f)
+      for (int ks = 0; ks < KF; ++ks)
+        for (int mt = 0; mt < MT; ++mt)
+          for (int l = 0; l < 64; ++l) {
+            const int i = 16 * mt + l % 16, m = 4 * ks + l / 16;
+            if (i < Np && m < Nfp)
+              af[(((size_t)f * KF + ks) * MT + mt) * 64 + l] =
+                  (f == 0 ? 2.0 : -2.0) * R.LIFT[(size_t)i * NF + f * Nfp + m];
+          }
     d_Avol = dalloc(rs * av.size());
     d_Alift = dalloc(rs * al.size());
-    if (!d_Avol || !d_Alift) return fail(DGW_ENOMEM, "device allocation failed (operators)");
+    d_Alf = dalloc(rs * af.size());
+    if (!d_Avol || !d_Alift || !d_Alf)
+      return fail(DGW_ENOMEM, "device allocation failed (operators)");
     if (precision == 64) {
       if ((rc = upload(d_Avol, av.data(), rs * av.size()))) return rc;
       if ((rc = upload(d_Alift, al.data(), rs * al.size()))) return rc;
+      if ((rc = upload(d_Alf, af.data(), rs * af.size()))) return rc;
     } else {
-      std::vector<float> avf(av.begin(), av.end()), alf(al.begin(), al.end());
+      std::vector<float> avf(av.begin(), av.end()), alf(al.begin(), al.end()),
+          aff(af.begin(), af.end());
       if ((rc = upload(d_Avol, avf.data(), rs * avf.size()))) return rc;
       if ((rc = upload(d_Alift, alf.data(), rs * alf.size()))) return rc;
+      if ((rc = upload(d_Alf, aff.data(), rs * aff.size()))) return rc;
     }
   }
   std::vector<int32_t> fm(R.fmask.begin(), R.fmask.end());
@@ -448,6 +469,7 @@ void dgw_destroy(dgw_ctx *c) {
   c->invalidate_graph();
   c->free_adjoint();
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->adj_ev) (void)hipEventDestroy(e);
   std::vector<void *> all = c->owned;
   for (void *p : all) c->dfree(p);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -828,6 +850,10 @@ int dgw_set_launch(dgw_ctx *c, int kernel, int elems_per_block, int wgs_per_cu) 
   if (!c) return DGW_EINVAL;
   if (!stage_kernel_supported(kernel, c->R.N, c->precision))
     return c->fail(DGW_EINVAL, "stage kernel not available for this order/precision");
+  if (kernel == 2 && c->have_aniso)
+    return c->fail(DGW_EINVAL, "stage kernel 2 supports isotropic elements only");
+  if (kernel == 2 && wgs_per_cu != 0)
+    return c->fail(DGW_EINVAL, "stage kernel 2 runs one work-group per block (wgs_per_cu 0)");
   std::vector<int> ch = stage_block_choices(kernel, c->R.N, c->precision);
   if (elems_per_block == 0) elems_per_block = ch[0];
   if (std::find(ch.begin(), ch.end(), elems_per_block) == ch.end())
@@ -885,6 +911,13 @@ int dgw_stage_kernel_ms(dgw_ctx *c, double *ms, int64_t *launches) {
   if (!c || !ms) return DGW_EINVAL;
   *ms = c->timed_ms;
   if (launches) *launches = c->timed_launches;
+  return DGW_OK;
+}
+
+int dgw_adjoint_stage_ms(dgw_ctx *c, double *ms, int64_t *stages) {
+  if (!c || !ms) return DGW_EINVAL;
+  *ms = c->adj_ms;
+  if (stages) *stages = c->adj_timed;
   return DGW_OK;
 }
 

@@ -78,6 +78,9 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *kernel,
   for (int kv : {0, 1})
     for (int be : stage_block_choices(kv, c->R.N, c->precision))
       for (int w : {0, 1, 2, 3, 4, 8, 16}) opts.push_back({kv, be, w});
+  // the minimal-form kernel: one shape (16 elements, one work-group each)
+  if (!c->have_aniso)
+    for (int be : stage_block_choices(2, c->R.N, c->precision)) opts.push_back({2, be, 0});
   auto report = [&](const Shape &o) {
     if (kernel) *kernel = o.kernel;
     if (elems_per_block) *elems_per_block = o.be;

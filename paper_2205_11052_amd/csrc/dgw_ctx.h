@@ -24,6 +24,7 @@ struct dgw_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   bool device_ready = false;
+  int device = 0;                   // HIP device the context's data lives on
   void *(*alloc_fn)(size_t, void *) = nullptr;
   void (*free_fn)(void *, void *) = nullptr;
   void *alloc_user = nullptr;
@@ -48,6 +49,7 @@ struct dgw_ctx {
   uint8_t *d_nbnode = nullptr, *d_nbfnode = nullptr;
   void *d_DrT = nullptr, *d_DsT = nullptr, *d_DtT = nullptr, *d_LIFTT = nullptr;
   void *d_Avol = nullptr, *d_Alift = nullptr;   // MFMA operator fragments
+  void *d_Alf = nullptr;                         // per-face lift fragments
   double *d_M = nullptr;
   void *d_q[2] = {nullptr, nullptr};
   void *d_res = nullptr;
@@ -87,6 +89,11 @@ struct dgw_ctx {
   int ev_pool_used = 0;
   double timed_ms = 0;
   int64_t timed_launches = 0;
+  // reverse-stage timing (dgw_adjoint with timing on): event pairs around
+  // the first reverse stages of the sweep, their average
+  std::vector<hipEvent_t> adj_ev;
+  double adj_ms = 0;
+  int64_t adj_timed = 0;
 
   // differentiation state (adjoint.cpp)
   struct Adjoint;
@@ -135,6 +142,7 @@ inline void stage_args(const dgw_ctx *c, dgw::StageArgs<real> &a, const void *in
   a.LIFTT = (const real *)c->d_LIFTT;
   a.Avol = (const real *)c->d_Avol;
   a.Alift = (const real *)c->d_Alift;
+  a.Alf = (const real *)c->d_Alf;
   a.fmask = c->d_fmask;
   a.K = c->mesh.K;
   a.shot_stride = c->mesh.K * 9 * c->R.Np;

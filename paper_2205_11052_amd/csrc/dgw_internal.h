@@ -94,6 +94,10 @@ struct StageArgs {
   // Avol[a][ks][mt][64] = D_a[16 mt + l % 16][4 ks + l / 16],
   // Alift[ks][mt][64] = LIFT[16 mt + l % 16][4 ks + l / 16], zero-padded
   const real *Avol, *Alift;
+  // per-face lift fragments of the minimal-form kernel (kernel 2):
+  // Alf[f][ks][mt][64] = c_f LIFT[16 mt + l % 16][f Nfp + 4 ks + l / 16] for
+  // 4 ks + l / 16 < Nfp, else 0; c_0 = 2, c_1 = c_2 = c_3 = -2
+  const real *Alf;
   const int32_t *fmask;         // [4 Nfp]
   int64_t K;
   int64_t shot_stride;          // K * 9 * Np
@@ -178,15 +182,23 @@ hipError_t launch_set_steps(int64_t *steps, int nshots, int64_t value,
                             hipStream_t st);
 
 // Launchers (kernels.hip); return the launch error.
-// kernel 0 (one thread per element node on the vector ALUs) or 1 (the
+// kernel 0 (one thread per element node on the vector ALUs), 1 (the
 // volume and lift contractions as one GEMM on the matrix cores), both with
-// 256 threads per work-group; with args.aniso set each runs its
-// anisotropic form: be = elements per work-group,
+// 256 threads per work-group, with args.aniso set each running its
+// anisotropic form, or 2 (the minimal-form matrix-core kernel of
+// stage_split.hip; isotropic only): be = elements per work-group,
 // wpc = persistent work-groups per compute unit (0: one work-group per block
 // of elements).  ncu = compute units.
 hipError_t launch_stage(int kernel, int N, int precision, int be, int wpc,
                         int ncu, int nshots, const void *args, hipStream_t st);
 bool stage_kernel_supported(int kernel, int N, int precision);
+// Kernel 2 (stage_split.hip): the minimal-form matrix-core kernel, 16
+// elements per work-group, isotropic elements only, orders 1-4 in FP64 and
+// 1-6 in FP32.
+bool stage_split_supported(int N, int precision);
+int stage_split_block();
+hipError_t launch_stage_split(int N, int precision, int nshots, const void *args,
+                              hipStream_t st);
 hipError_t launch_receivers(int precision, int nshots, const RecArgs &a,
                             hipStream_t st);
 // aniso: [K][DGW_ANI] or null (isotropic elements)

@@ -370,6 +370,15 @@ class Solver:
         self._check(self.lib.dgw_enable_timing(self._ctx, 1 if on else 0),
                     "dgw_enable_timing")
 
+    def adjoint_stage_ms(self):
+        """(average ms of one reverse stage, stages timed) of the last
+        adjoint() run with timing enabled."""
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(self.lib.dgw_adjoint_stage_ms(self._ctx, C.byref(ms), C.byref(n)),
+                    "dgw_adjoint_stage_ms")
+        return ms.value, n.value
+
     def stage_kernel_ms(self):
         ms = C.c_double()
         n = C.c_int64()

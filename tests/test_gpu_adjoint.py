@@ -126,9 +126,10 @@ def test_stale_forward_is_refused():
     case = _small_case(2, nsteps=12, seed=3)
     say("case stale adjoint state")
     s = _gpu(case, 64)
+    s.set_receivers(0, case["rec"], case["nsteps"] + 8)   # room for the extra step
     changes = [lambda: s.set_material(*case["start"]), lambda: s.zero_fields(),
                lambda: s.step(1), lambda: s.set_dt(case["dt"]),
-               lambda: s.set_receivers(0, case["rec"], case["nsteps"])]
+               lambda: s.set_receivers(0, case["rec"], case["nsteps"] + 8)]
     for change in changes:
         s.zero_fields()
         s.forward_checkpointed(case["nsteps"], 4, case["d_obs"][None])

@@ -41,7 +41,8 @@ def _isotropic_in_fluid(q, fluid):
 
 
 @pytest.mark.parametrize("N,kernel,prec", [(3, 0, 64), (3, 1, 64), (4, 0, 64),
-                                           (4, 1, 64), (4, 1, 32), (4, 0, 32)])
+                                           (4, 1, 64), (4, 1, 32), (4, 0, 32),
+                                           (3, 2, 64), (4, 2, 64), (4, 2, 32)])
 def test_fluid_solid_matches_oracle(N, kernel, prec):
     mesh = W.kuhn_cube(3, 1.0)          # free-surface top, absorbing sides
     (rho, lam, mu), fluid = _fluid_over_solid(mesh, 80 + N, 0.6)

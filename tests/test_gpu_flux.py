@@ -29,7 +29,8 @@ def _random_medium(K, seed):
 
 @pytest.mark.parametrize("tau,N,kernel,prec", [
     (0.0, 3, 0, 64), (0.0, 3, 1, 64), (0.5, 4, 0, 64), (0.5, 4, 1, 64),
-    (0.3, 2, 1, 64), (0.0, 4, 1, 32), (0.5, 4, 0, 32)])
+    (0.3, 2, 1, 64), (0.0, 4, 1, 32), (0.5, 4, 0, 32), (0.0, 3, 2, 64),
+    (0.5, 4, 2, 64), (0.5, 4, 2, 32)])
 def test_flux_variant_matches_oracle(tau, N, kernel, prec):
     mesh = W.kuhn_cube(2, 1.0)          # free-surface top, absorbing sides
     K = mesh["etov"].shape[0]

@@ -54,11 +54,18 @@ def test_c0_periodic_plane_wave_fp64():
 
 
 # stage kernel variants: 0 = one thread per node on the vector ALUs,
-# 1 = volume and lift as one GEMM on the matrix cores
-KERNELS = (0, 1)
+# 1 = volume and lift as one GEMM on the matrix cores, 2 = the minimal-form
+# matrix-core kernel (orders 1-4 in FP64, 1-6 in FP32; 16 elements per
+# work-group, no persistent grid)
+KERNELS = (0, 1, 2)
 
 
-@pytest.mark.parametrize("N,kernel", [(N, kv) for kv in KERNELS for N in range(1, 7)])
+def supported(kernel, N, precision=64):
+    return kernel != 2 or N <= (4 if precision == 64 else 6)
+
+
+@pytest.mark.parametrize("N,kernel", [(N, kv) for kv in KERNELS for N in range(1, 7)
+                                      if supported(kv, N)])
 def test_all_orders_all_boundaries_fp64(N, kernel):
     mesh = W.kuhn_cube(2, 1.0)          # free-surface top, absorbing sides
     K = mesh["etov"].shape[0]
@@ -135,8 +142,8 @@ def test_full_size_layered_fp64_bench_launch():
     benchmark's autotuner can pick, two steps against the oracle."""
     w, dt, q0, q_ora, tr_ora = _full_c1_oracle()
     say("case full c1 fp64 K=%d" % w["K"])
-    shapes = [(kv, be, wpc) for kv in KERNELS for be in (7, 3)
-              for wpc in (0, 1, 2, 3, 4, 8, 16)]
+    shapes = [(kv, be, wpc) for kv in (0, 1) for be in (7, 3)
+              for wpc in (0, 1, 2, 3, 4, 8, 16)] + [(2, 16, 0)]
     s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
     s.set_source(0, w["source"], w["f0"], 0.05, w["amp"])
     s.set_receivers(0, w["receivers"], 8)
@@ -159,7 +166,7 @@ def test_full_size_layered_fp32_bench_launch(kernel):
     s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt, 32)
     s.set_source(0, w["source"], w["f0"], 0.05, w["amp"])
     s.set_receivers(0, w["receivers"], 8)
-    for be in (7, 3):
+    for be in ((7, 3) if kernel < 2 else (16,)):
         s.set_launch(kernel, be, 0)
         s.set_fields(0, q0)
         s.step(2)
@@ -259,7 +266,8 @@ def test_fp32_error_against_fp64_oracle(kernel):
     assert err <= FP32_TOL
 
 
-@pytest.mark.parametrize("N,kernel", [(N, kv) for kv in KERNELS for N in (4, 6)])
+@pytest.mark.parametrize("N,kernel", [(N, kv) for kv in KERNELS for N in (4, 6)
+                                      if supported(kv, N, 32)])
 def test_fp32_reduced_layered(N, kernel):
     w = _reduced_c1(n=4, N=N)
     say("case reduced c2 fp32 N=%d K=%d kernel=%d" % (N, w["K"], kernel))
@@ -320,8 +328,21 @@ def test_graph_replay_equals_eager_and_block_shapes_agree():
     for o in mouts[1:]:
         assert np.array_equal(mouts[0], o)
     assert rel_l2(mouts[0], outs[0]) <= FP64_TOL
+    # the minimal-form kernel: graph replay equals eager bitwise, and it
+    # equals variant 0 to rounding
+    souts = []
+    for timing in (False, True):
+        s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
+        s.set_launch(2, 16, 0)
+        s.enable_timing(timing)
+        s.set_source(0, w["source"], w["f0"], w["t0"], w["amp"])
+        s.set_fields(0, q0)
+        s.step(23)
+        souts.append(s.get_fields(0))
+    assert np.array_equal(souts[0], souts[1])
+    assert rel_l2(souts[0], outs[0]) <= FP64_TOL
     # a kernel variant or shape this build does not provide is refused
-    for bad in ((2, 0, 0), (0, 5, 0), (1, 5, 0), (0, 7, 65)):
+    for bad in ((3, 0, 0), (0, 5, 0), (1, 5, 0), (0, 7, 65), (2, 7, 0), (2, 16, 2)):
         with pytest.raises(DGWError) as ei:
             s.set_launch(*bad)
         assert ei.value.status == "DGW_EINVAL"
@@ -340,8 +361,9 @@ def test_batched_shots_match_single_shot_runs(precision, kernel):
     rec = np.array([[0.4, 0.4, 1.0], [0.6, 0.2, 1.0]])
     say("case batched shots precision=%d kernel=%d" % (precision, kernel))
     b = gpu_solver(mesh, N, rho, lam, mu, dt, precision, nshots=3)
-    # persistent grid looping over (shot, block) items
-    b.set_launch(kernel, 0, 2)
+    # persistent grid looping over (shot, block) items (kernel 2: one
+    # work-group per (shot, block) item)
+    b.set_launch(kernel, 0, 2 if kernel < 2 else 0)
     for i in range(3):
         b.set_source(i, srcs[i], 6.0, 0.1, 1.0, nsteps=lens[i])
         b.set_receivers(i, rec, 20)
@@ -366,11 +388,11 @@ def test_tiny_mesh_smaller_than_a_block_and_zero_steps():
     K = mesh["etov"].shape[0]
     rho, lam, mu = _random_medium(K, 8)
     say("case tiny mesh")
-    for N in (1, 4):
+    for N, kernel in ((1, 0), (4, 0), (1, 2), (4, 2)):
         P = oracle_problem(mesh, N)
         dt = P.suggest_dt(rho, lam, mu, 0.5)
         q0 = random_fields(K, P.Np, 9)
-        s = gpu_solver(mesh, N, rho, lam, mu, dt)
+        s = gpu_solver(mesh, N, rho, lam, mu, dt, kernel=kernel)
         s.set_fields(0, q0)
         s.step(0)
         assert np.array_equal(s.get_fields(0), q0)

@@ -38,7 +38,8 @@ def _points(mesh, elems):
 
 
 @pytest.mark.parametrize("N,kernel,prec", [(3, 0, 64), (3, 1, 64), (4, 0, 64),
-                                           (4, 1, 64), (4, 0, 32), (4, 1, 32)])
+                                           (4, 1, 64), (4, 0, 32), (4, 1, 32),
+                                           (3, 2, 64), (4, 2, 64), (4, 2, 32)])
 def test_general_mesh_matches_oracle(N, kernel, prec):
     mesh = W.general_mesh(4, 2.0, seed=21)
     K = mesh["etov"].shape[0]
@@ -77,7 +78,7 @@ def test_reordered_numbering_is_a_relabelling(method):
     src = _points(mesh, [101])[0]
     rec = _points(mesh, [7, 500, 1200])
     dt = None
-    for kernel in (0, 1):
+    for kernel in (0, 1, 2):
         outs = []
         for m, p in ((mesh, np.arange(K)), (mesh2, perm)):
             from paper_2205_11052_amd import Solver
@@ -121,7 +122,7 @@ def test_full_size_general_mesh_fp64():
     s = gpu_solver(mesh, 4, rho, lam, mu, dt)
     s.set_source(0, src, 2.0, 0.05, 1.0, moment=MOMENT)
     s.set_receivers(0, rec, 8)
-    for shape in ((1, 7, 0), (1, 3, 0), (0, 7, 0), (0, 3, 0), (1, 7, 3)):
+    for shape in ((1, 7, 0), (1, 3, 0), (0, 7, 0), (0, 3, 0), (1, 7, 3), (2, 16, 0)):
         s.set_launch(*shape)
         s.set_fields(0, q0)
         s.step(2)

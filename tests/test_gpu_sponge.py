@@ -38,7 +38,8 @@ def _unit_sponge(mesh, sigma_max=6.0):
 
 @pytest.mark.parametrize("N,kernel,prec,tau", [
     (3, 0, 64, 1.0), (3, 1, 64, 1.0), (4, 0, 64, 1.0), (4, 1, 64, 1.0),
-    (4, 1, 64, 0.5), (4, 0, 32, 1.0), (4, 1, 32, 1.0)])
+    (4, 1, 64, 0.5), (4, 0, 32, 1.0), (4, 1, 32, 1.0), (3, 2, 64, 1.0),
+    (4, 2, 64, 0.5), (4, 2, 32, 1.0)])
 def test_sponge_matches_oracle(N, kernel, prec, tau):
     mesh = W.kuhn_cube(3, 1.0)
     K = mesh["etov"].shape[0]
