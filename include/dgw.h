@@ -161,6 +161,16 @@ int dgw_shot_steps(dgw_ctx *ctx, int shot, int64_t *steps);
  * the stress term), accumulated in FP64 on the device. */
 int dgw_energy(dgw_ctx *ctx, int shot, double *E);
 
+/* dgw_energy without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid it).  Same quantity and arguments as dgw_energy; its partial
+ * sums live in a static device array of the library (one per GPU, 65537
+ * doubles, held until the process ends), so it supports meshes of at most
+ * 16,777,216 elements (DGW_ERANGE beyond).  It allocates nothing and frees
+ * nothing; it enqueues two kernels and an 8-byte copy on the context's
+ * stream and synchronizes it.  Calls that overlap on one GPU (from several
+ * threads or contexts) share the array and race: serialize them. */
+int dgw_energy_noalloc(dgw_ctx *ctx, int shot, double *E);
 
 /* DGW_ENONFINITE if any field value of any shot is NaN or infinite. */
 int dgw_check_finite(dgw_ctx *ctx);

@@ -39,6 +39,7 @@ SIGNATURES = {
     "dgw_read_traces": (C.c_int, [_P, C.c_int, _D, _I64, _PI64]),
     "dgw_shot_steps": (C.c_int, [_P, C.c_int, _PI64]),
     "dgw_energy": (C.c_int, [_P, C.c_int, _D]),
+    "dgw_energy_noalloc": (C.c_int, [_P, C.c_int, _D]),
     "dgw_check_finite": (C.c_int, [_P]),
     "dgw_ref_nodes": (C.c_int, [C.c_int, _D]),
     "dgw_ref_operators": (C.c_int, [C.c_int, _D, _D, _D, _D, _D]),

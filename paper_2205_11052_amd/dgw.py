@@ -290,6 +290,14 @@ class Solver:
                     "dgw_energy")
         return e.value
 
+    def energy_noalloc(self, shot=0):
+        """dgw_energy through the library's static scratch (no device
+        allocation)."""
+        e = C.c_double()
+        self._check(self.lib.dgw_energy_noalloc(self._ctx, shot, C.byref(e)),
+                    "dgw_energy_noalloc")
+        return e.value
+
     def check_finite(self):
         self._check(self.lib.dgw_check_finite(self._ctx), "dgw_check_finite")
 
