@@ -15,21 +15,25 @@
 // and face 0 feeds every direction equally, so it has an accumulator of its
 // own that is added to each direction.
 //
-// Work item: 16 consecutive elements of one shot (one 16-column MFMA tile per
-// component), 6 waves:
+// Work item: 32 consecutive elements of one shot in two tile sets of 16 (one
+// 16-column MFMA tile per component and set), 12 waves, six per set:
 //   waves 0-2, velocity component k: rhs_k = sum_a D_a u_{k,a} + LIFT F_k
 //     with u_{k,a} = (1/rho) sum_b X^-1[a][b] sigma_kb formed per node from
 //     the fields (read from global memory in MFMA lane order) and F_k the
 //     lifted velocity flux (LDS): one accumulator per row tile;
 //   waves 3-5, velocity component c: D_a v_c for a = 0..2 and the face
 //     lifts, accumulated per direction (plus face 0 apart).
+// One 12-wave work-group fills a CU at the kernel's register budget (three
+// waves per SIMD); two six-wave work-groups of 16 elements would not be
+// co-resident, since each puts two waves on two of the SIMDs.
 // Phases: (1) per-element data to LDS, own and neighbour traces of the
 // block's face nodes to registers; (2) exact Riemann flux per face node,
 // six quantities to LDS (Fscale dt*/rho and dv); (3) the GEMMs; (4) the
 // gradient waves turn their accumulators into G and stage it in LDS over
-// the dead flux buffer, while the velocity waves update their component
-// straight from the accumulators; (5) all threads form the stress rates
-// from G per node and update the six stress components.
+// the dead flux buffer; (5) the stress rates per node from G, then the whole
+// right-hand side (stresses, and the velocity waves' accumulators) to LDS
+// in the block's element-field-node order; (6) the point source, sponge and
+// LSERK update over the block's contiguous span with 16-byte accesses.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -43,8 +47,10 @@ namespace {
 
 using namespace stagec;
 
-constexpr int kBE = 16;                 // elements per work item (tile width)
-constexpr int kWaves = 6;
+constexpr int kTile = 16;               // elements per MFMA column tile
+constexpr int kSets = 2;                // tile sets per work-group
+constexpr int kBE = kTile * kSets;      // elements per work item
+constexpr int kWaves = 6 * kSets;       // six waves per tile set
 constexpr int kThr = 64 * kWaves;
 
 template <int N, typename real>
@@ -54,13 +60,16 @@ struct SplitSz {
   static constexpr int KS = (Np + 3) / 4;     // k-steps of one reference derivative
   static constexpr int KL = NF / 4;           // k-steps of the velocity lift
   static constexpr int KF = (Nfp + 3) / 4;    // k-steps of one face's lift
-  static constexpr int FLUX = 6 * NF * kBE;   // flux buffer [6][NF][kBE]
-  // gradient staging [9][kBE][NpG]: rows of odd length, so the per-lane
-  // writes from the accumulators (lanes across elements) spread over the
-  // LDS banks and the per-node reads (threads across nodes) are contiguous
-  static constexpr int NpG = Np % 2 ? Np : Np + 1;
+  // LDS rows of odd length (in reals or doubles), so lanes that walk across
+  // the block's elements at a fixed offset fall in distinct banks
+  static constexpr int MS = DGW_META + 1;     // per-element data row
+  static constexpr int NFp = NF | 1;          // flux rows [6][kBE][NFp]
+  static constexpr int NpG = Np | 1;          // gradient rows [9][kBE][NpG]
+  static constexpr int FLUX = 6 * kBE * NFp;
   static constexpr int GRAD = 9 * kBE * NpG;
-  static constexpr int BUF = FLUX > GRAD ? FLUX : GRAD;
+  static constexpr int RHS = kBE * 9 * Np;    // right-hand side, the block's order
+  static constexpr int B1 = FLUX > GRAD ? FLUX : GRAD;
+  static constexpr int BUF = B1 > RHS ? B1 : RHS;
   static constexpr int FI = (kBE * NF + kThr - 1) / kThr;   // face items per thread
   static constexpr int NI = (kBE * Np + kThr - 1) / kThr;   // node items per thread
 };
@@ -77,10 +86,12 @@ stage_split_kernel(StageArgs<real> A, int64_t nblk, int64_t total) {
   using M = Mma<real>;
   using v4 = typename M::v4;
   constexpr int Np = Z::Np, Nfp = Z::Nfp, NF = Z::NF, MT = Z::MT, KS = Z::KS,
-                KL = Z::KL, KF = Z::KF, FI = Z::FI, NI = Z::NI, NpG = Z::NpG;
-  __shared__ double smeta[kBE * DGW_META];
+                KL = Z::KL, KF = Z::KF, FI = Z::FI, NI = Z::NI, MS = Z::MS,
+                NFp = Z::NFp, NpG = Z::NpG;
+  __shared__ double smeta[kBE * MS];
   __shared__ double ssig[kBE];
   __shared__ __attribute__((aligned(16))) real sbuf[Z::BUF];
+  __shared__ real sf0[3 * kBE * NpG];   // face-0 lift of each velocity component
 
   const int64_t item = xcd_item(blockIdx.x, total);
   const int shot = (int)(item / nblk);
@@ -114,20 +125,20 @@ stage_split_kernel(StageArgs<real> A, int64_t nblk, int64_t total) {
 #pragma unroll
     for (int u = 0; u < MU; ++u) {
       const int j = tid + u * kThr;
-      if (j < nE * DGW_META) smeta[j] = mreg[u];
+      if (j < nE * DGW_META) smeta[(j / DGW_META) * MS + j % DGW_META] = mreg[u];
     }
     if (tid < nE) ssig[tid] = A.sponge ? sgv : 0.0;
   }
-  // face items t = fm * kBE + e (element fastest, so the flux writes to
-  // the [q][fm][kBE] buffer are contiguous across a wave)
+  // face items t = e * NF + fm (face node fastest: a wave's gathers stay
+  // within one or two elements)
   real qm[FI][9], qp[FI][9];
   int cnv[FI];
 #pragma unroll
   for (int u = 0; u < FI; ++u) {
     const int t = tid + u * kThr;
-    const bool ok = t < kBE * NF && (t & (kBE - 1)) < nE;
+    const bool ok = t < nE * NF;
     const int tt = ok ? t : 0;
-    const int e = tt & (kBE - 1), fm = tt / kBE, f = fm / Nfp;
+    const int e = tt / NF, fm = tt - e * NF, f = fm / Nfp;
     const int64_t k = k0 + e;
     const int cn = A.conn[k * 4 + f];
     const int nb = A.nbnode[k * NF + fm];
@@ -148,9 +159,9 @@ stage_split_kernel(StageArgs<real> A, int64_t nblk, int64_t total) {
 #pragma unroll
   for (int u = 0; u < FI; ++u) {
     const int t = tid + u * kThr;
-    if (t >= kBE * NF || (t & (kBE - 1)) >= nE) continue;
-    const int e = t & (kBE - 1), fm = t / kBE, f = fm / Nfp;
-    const double *g = smeta + e * DGW_META;
+    if (t >= nE * NF) continue;
+    const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
+    const double *g = smeta + e * MS;
     real p[9];
     const int cn = cnv[u];
     if (cn >= 0) {
@@ -191,32 +202,36 @@ stage_split_kernel(StageArgs<real> A, int64_t nblk, int64_t total) {
     const real ux = tu * (kn * nx + kTx) + hc * dvx;
     const real uy = tu * (kn * ny + kTy) + hc * dvy;
     const real uz = tu * (kn * nz + kTz) + hc * dvz;
-    real *d = sbuf + fm * kBE + e;
-    d[0 * NF * kBE] = fs * wx * ri;
-    d[1 * NF * kBE] = fs * wy * ri;
-    d[2 * NF * kBE] = fs * wz * ri;
-    d[3 * NF * kBE] = ux;
-    d[4 * NF * kBE] = uy;
-    d[5 * NF * kBE] = uz;
+    real *d = sbuf + e * NFp + fm;
+    d[0 * kBE * NFp] = fs * wx * ri;
+    d[1 * kBE * NFp] = fs * wy * ri;
+    d[2 * kBE * NFp] = fs * wz * ri;
+    d[3 * kBE * NFp] = ux;
+    d[4 * kBE * NFp] = uy;
+    d[5 * kBE * NFp] = uz;
   }
   __syncthreads();
 
-  // ---- 3. the GEMMs: one 16-column tile (16 elements, one component) per wave
-  const int wave = tid >> 6, lane = tid & 63, g = lane >> 4, col = lane & 15;
+  // ---- 3. the GEMMs: one 16-column tile (16 elements, one component) per
+  // wave; waves 6 h .. 6 h + 5 own tile set h (elements 16 h .. 16 h + 15)
+  const int wave = tid >> 6, lane = tid & 63, g = lane >> 4;
+  const int role = wave % 6, col = (wave / 6) * kTile + (lane & 15);
   const int ec = col < nE ? col : nE - 1;          // clamped element of this column
   const int64_t kc = k0 + ec;
   const real *qe = qin + kc * 9 * Np;
-  const double *gm = smeta + ec * DGW_META;
-  const bool velw = wave < 3;
-  const int comp = velw ? wave : wave - 3;
-  v4 acc[MT], accg[3][MT], acc0[MT];
+  const double *gm = smeta + ec * MS;
+  const bool velw = role < 3;
+  const int comp = velw ? role : role - 3;
+  // one accumulator array for both roles (a wave runs one role, so sharing
+  // the registers keeps the other role's tiles out of each branch):
+  // velocity waves use acc[0] (their component's right-hand side) and
+  // acc[1] (the face-0 lift of velocity component comp, for the gradient
+  // waves); gradient waves use acc[a] for reference direction a
+  v4 acc[3][MT];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    acc[mt] = v4{0, 0, 0, 0};
-    acc0[mt] = v4{0, 0, 0, 0};
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) accg[a][mt] = v4{0, 0, 0, 0};
-  }
+    for (int mt = 0; mt < MT; ++mt) acc[a][mt] = v4{0, 0, 0, 0};
   if (velw) {
     // u_{k,a} = (1/rho) sum_b X^-1[a][b] sigma_kb
     const real ri = (real)gm[M_RHOINV];
@@ -240,179 +255,256 @@ stage_split_kernel(StageArgs<real> A, int64_t nblk, int64_t total) {
         const real b = cf[a][0] * x0 + cf[a][1] * x1 + cf[a][2] * x2;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-          acc[mt] = M::mma(Av[((a * KS + ks) * MT + mt) * 64], b, acc[mt]);
+          acc[0][mt] = M::mma(Av[((a * KS + ks) * MT + mt) * 64], b, acc[0][mt]);
       }
     }
-    const real *fl = sbuf + comp * NF * kBE + col;
+    const real *fl = sbuf + (comp * kBE + col) * NFp;
     const real *Al = A.Alift + lane + oz;
 #pragma unroll
     for (int ks = 0; ks < KL; ++ks) {
-      const real b = fl[(4 * ks + g) * kBE];
+      const real b = fl[4 * ks + g];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
-        acc[mt] = M::mma(Al[(ks * MT + mt) * 64], b, acc[mt]);
+        acc[0][mt] = M::mma(Al[(ks * MT + mt) * 64], b, acc[0][mt]);
+    }
+    // face-0 lift of velocity component comp (Alf[0] = 2 LIFT_0): the same
+    // term for every reference direction of that component's gradient, so
+    // it is computed once here and added in the stress assembly
+    const real *fu = sbuf + ((3 + comp) * kBE + col) * NFp;
+    const real *Af = A.Alf + lane + oz;
+#pragma unroll
+    for (int ks = 0; ks < KF; ++ks) {
+      const int m = 4 * ks + g, mm = m < Nfp ? m : Nfp - 1;
+      real b = fu[mm];
+      b = m < Nfp ? b : (real)0;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        acc[1][mt] = M::mma(Af[(ks * MT + mt) * 64], b, acc[1][mt]);
     }
   } else {
     const real *vc = qe + comp * Np;
     const real *Av = A.Avol + lane + oz;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
+    // software-pipelined: the operator fragments and field value of k-step
+    // ks + 1 are loaded before the nine MFMAs of k-step ks, and the
+    // scheduling groups keep that order (without them the scheduler sinks
+    // every load onto its MFMA and waits on each)
+    real an[3][MT], bn;
+    auto fetch = [&](int ks) {
       const int j = 4 * ks + g, jj = j < Np ? j : Np - 1;
-      real b = vc[jj];
-      b = j < Np ? b : (real)0;
+      bn = vc[jj];
+      bn = j < Np ? bn : (real)0;
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-          accg[a][mt] = M::mma(Av[((a * KS + ks) * MT + mt) * 64], b, accg[a][mt]);
+        for (int mt = 0; mt < MT; ++mt) an[a][mt] = Av[((a * KS + ks) * MT + mt) * 64];
+    };
+    fetch(0);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      real ac[3][MT];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) ac[a][mt] = an[a][mt];
+      const real b = bn;
+      if (ks + 1 < KS) fetch(ks + 1);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[a][mt] = M::mma(ac[a][mt], b, acc[a][mt]);
+      if (ks + 1 < KS) __builtin_amdgcn_sched_group_barrier(0x020, 3 * MT + 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 3 * MT, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    // face lifts: Alf[f] = c_f LIFT_f (c_0 = 2, c_{1,2,3} = -2), face f > 0
-    // into direction f - 1, face 0 apart
-    const real *fu = sbuf + (3 + comp) * NF * kBE + col;
+    // lifts of faces 1-3: Alf[f] = -2 LIFT_f into direction f - 1 (face 0
+    // is lifted by the velocity wave of this component)
+    // (software-pipelined like the volume loop: operator fragments three
+    // k-steps ahead)
+    const real *fu = sbuf + ((3 + comp) * kBE + col) * NFp;
     const real *Af = A.Alf + lane + oz;
+    constexpr int NIT = 3 * KF, DIST = 3;
+    real ring[NIT][MT];
+    auto fetchf = [&](int it) {
+      const int f = 1 + it / KF, ks = it - (it / KF) * KF;
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
+      for (int mt = 0; mt < MT; ++mt) ring[it][mt] = Af[((f * KF + ks) * MT + mt) * 64];
+    };
 #pragma unroll
-      for (int ks = 0; ks < KF; ++ks) {
-        const int m = 4 * ks + g, mm = m < Nfp ? m : Nfp - 1;
-        real b = fu[(f * Nfp + mm) * kBE];
-        b = m < Nfp ? b : (real)0;
+    for (int it = 0; it < DIST && it < NIT; ++it) fetchf(it);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const real a = Af[((f * KF + ks) * MT + mt) * 64];
-          if (f == 0)
-            acc0[mt] = M::mma(a, b, acc0[mt]);
-          else
-            accg[f - 1][mt] = M::mma(a, b, accg[f - 1][mt]);
-        }
-      }
+    for (int it = 0; it < NIT; ++it) {
+      const int f = 1 + it / KF, ks = it - (it / KF) * KF;
+      if (it + DIST < NIT) fetchf(it + DIST);
+      const int m = 4 * ks + g, mm = m < Nfp ? m : Nfp - 1;
+      real b = fu[f * Nfp + mm];
+      b = m < Nfp ? b : (real)0;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[f - 1][mt] = M::mma(ring[it][mt], b, acc[f - 1][mt]);
+      if (it + DIST < NIT) __builtin_amdgcn_sched_group_barrier(0x020, MT, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, MT, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
   __syncthreads();   // every wave is done with the flux buffer
 
-  // ---- 4. gradient waves stage G; velocity waves update their component ----
-  const real ra = (real)A.rk_a, rb = (real)A.rk_b, rdt = (real)A.dt;
-  constexpr bool kStream = N >= 4;
-  if (!velw) {
-    real X[9];
-#pragma unroll
-    for (int u = 0; u < 9; ++u) X[u] = (real)gm[M_XINV + u];
-    if (col < nE) {
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 16 * mt + M::row(g, r);
-          if (i < Np) {
-            const real d0 = accg[0][mt][r] + acc0[mt][r], d1 = accg[1][mt][r] + acc0[mt][r],
-                       d2 = accg[2][mt][r] + acc0[mt][r];
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-              sbuf[((comp * 3 + b) * kBE + col) * NpG + i] =
-                  X[b] * d0 + X[3 + b] * d1 + X[6 + b] * d2;
-          }
-        }
-    }
-  } else if (col < nE) {
-    const real sg = (real)ssig[col];
-    const int64_t base = kc * 9 * Np + comp * Np;
-    real rold[MT][4], qv[MT][4];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * mt + M::row(g, r), ii = i < Np ? i : Np - 1;
-        qv[mt][r] = qin[base + ii];
-        if (first)
-          rold[mt][r] = (real)0;
-        else if constexpr (kStream)
-          rold[mt][r] = __builtin_nontemporal_load(res + base + ii);
-        else
-          rold[mt][r] = res[base + ii];
-      }
+  // ---- 4. gradient waves: sum_a X^-1[a][b] (D_a v_c + lifts of faces 1-3)
+  // to LDS; velocity waves: the face-0 lifts to LDS
+  if (velw && col < nE) {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * mt + M::row(g, r);
-        if (i >= Np) continue;
-        real rhs = acc[mt][r];
-        if (A.sponge) rhs -= sg * qv[mt][r];
-        const real rn = first ? rdt * rhs : ra * rold[mt][r] + rdt * rhs;
-        const real qn = qv[mt][r] + rb * rn;
-        if constexpr (kStream) {
-          __builtin_nontemporal_store(rn, res + base + i);
-          if constexpr (sizeof(real) == 8)
-            __builtin_nontemporal_store(qn, qout + base + i);
-          else
-            qout[base + i] = qn;
-        } else {
-          res[base + i] = rn;
-          qout[base + i] = qn;
+        if (i < Np) sf0[(comp * kBE + col) * NpG + i] = acc[1][mt][r];
+      }
+  }
+  if (!velw && col < nE) {
+    real X[9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) X[u] = (real)gm[M_XINV + u];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * mt + M::row(g, r);
+        if (i < Np) {
+          const real d0 = acc[0][mt][r], d1 = acc[1][mt][r], d2 = acc[2][mt][r];
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+            sbuf[((comp * 3 + b) * kBE + col) * NpG + i] =
+                X[b] * d0 + X[3 + b] * d1 + X[6 + b] * d2;
         }
       }
   }
   __syncthreads();
 
-  // ---- 5. stress rates from G per node, source, update of the stresses ----
+  // ---- 5. stress rates from G per node (to registers); G_cb gains the
+  // face-0 lift of v_c times sum_a X^-1[a][b] ----
+  real srhs[NI][6];
+#pragma unroll
+  for (int u = 0; u < NI; ++u) {
+    const int t = tid + u * kThr;
+    const int tt = t < nE * Np ? t : 0;
+    const int e = tt / Np, i = tt - e * Np;
+    const double *ge = smeta + e * MS;
+    real G[3][3], xs[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      xs[b] = (real)ge[M_XINV + b] + (real)ge[M_XINV + 3 + b] + (real)ge[M_XINV + 6 + b];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const real f0 = sf0[(c * kBE + e) * NpG + i];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) G[c][b] = sbuf[((c * 3 + b) * kBE + e) * NpG + i] + xs[b] * f0;
+    }
+    const real la = (real)ge[M_LAM], mu = (real)ge[M_MU];
+    const real divv = G[0][0] + G[1][1] + G[2][2];
+    srhs[u][0] = la * divv + 2 * mu * G[0][0];
+    srhs[u][1] = la * divv + 2 * mu * G[1][1];
+    srhs[u][2] = la * divv + 2 * mu * G[2][2];
+    srhs[u][3] = mu * (G[1][2] + G[2][1]);
+    srhs[u][4] = mu * (G[0][2] + G[2][0]);
+    srhs[u][5] = mu * (G[0][1] + G[1][0]);
+  }
+  __syncthreads();   // every G value is read
+  // residual loads of this thread's update items (16-byte vectors over the
+  // block's contiguous span), issued here -- once the gradient values are
+  // consumed, which keeps them clear of the register peak of the stress
+  // assembly -- so their latency overlaps the staging below (the state is
+  // loaded in the update loop)
+  using SP = Span16<real>;
+  constexpr int UV = (kBE * 9 * Np / SP::VW + kThr - 1) / kThr;
+  constexpr bool kStream = N >= 4;
+  const SP sp(shot * A.shot_stride + k0 * 9 * Np, nE * 9 * Np);
+  real *rs = res + k0 * 9 * Np, *qo = qout + k0 * 9 * Np;
+  const real *qb = qin + k0 * 9 * Np;
+  typename SP::vec rv[UV];
+#pragma unroll
+  for (int u = 0; u < UV; ++u) {
+    const int j = tid + u * kThr;
+    const int jj = j < sp.nv ? j : (sp.nv > 0 ? sp.nv - 1 : 0);
+    const typename SP::vec *rp = (const typename SP::vec *)(rs + sp.hd) + jj;
+    if (first)
+      rv[u] = typename SP::vec{};
+    else if constexpr (kStream)
+      rv[u] = __builtin_nontemporal_load(rp);
+    else
+      rv[u] = *rp;
+  }
+  const int tl0 = sp.hd + SP::VW * sp.nv;
+  const real qh = tid < sp.hd ? qb[tid] : (real)0, qt = tid < sp.tl ? qb[tl0 + tid] : (real)0;
+  const real rh = (!first && tid < sp.hd) ? rs[tid] : (real)0;
+  const real rt = (!first && tid < sp.tl) ? rs[tl0 + tid] : (real)0;
+  // the whole right-hand side to LDS in the block's (element, field, node)
+  // order: stresses from the node items, velocities from the accumulators
+#pragma unroll
+  for (int u = 0; u < NI; ++u) {
+    const int t = tid + u * kThr;
+    if (t < nE * Np) {
+      const int e = t / Np, i = t - e * Np;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sbuf[(e * 9 + 3 + c) * Np + i] = srhs[u][c];
+    }
+  }
+  if (velw && col < nE) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * mt + M::row(g, r);
+        if (i < Np) sbuf[(col * 9 + comp) * Np + i] = acc[0][mt][r];
+      }
+  }
+  __syncthreads();
+
+  // ---- 6. point source, sponge and LSERK update over the contiguous span
+  const real ra = (real)A.rk_a, rb = (real)A.rk_b, rdt = (real)A.dt;
   const int64_t es = (int64_t)A.src_elem[shot] - k0;   // source element in block
   double s = 0.0;
   const double *spar = A.src_par + 10 * shot;
   if (es >= 0 && es < nE) s = ricker_d(((double)step + A.rk_c) * A.dt, spar[6], spar[7], spar[8]);
+  auto update = [&](int t, real qold, real rold) -> real2v<real> {
+    real rhs = sbuf[t];
+    const int e = t / (9 * Np), ci = t - e * 9 * Np, c = ci / Np, i = ci - c * Np;
+    if (e == es && c >= 3) rhs += (real)(s * spar[c - 3] * A.src_vec[shot * Np + i]);
+    if (A.sponge) rhs -= (real)ssig[e] * qold;
+    const real rn = first ? rdt * rhs : ra * rold + rdt * rhs;
+    return {rn, qold + rb * rn};
+  };
 #pragma unroll
-  for (int u = 0; u < NI; ++u) {
-    const int t = tid + u * kThr;
-    if (t >= nE * Np) continue;
-    const int e = t / Np, i = t - e * Np;
-    const double *ge = smeta + e * DGW_META;
-    real G[3][3];
+  for (int u = 0; u < UV; ++u) {
+    const int j = tid + u * kThr;
+    if (j >= sp.nv) continue;
+    const int b = sp.hd + SP::VW * j;
+    const typename SP::vec qv = *(const typename SP::vec *)(qb + b);
+    typename SP::vec nr, nq;
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) G[c][b] = sbuf[((c * 3 + b) * kBE + e) * NpG + i];
-    const real la = (real)ge[M_LAM], mu = (real)ge[M_MU];
-    const real divv = G[0][0] + G[1][1] + G[2][2];
-    real rhs[6];
-    rhs[0] = la * divv + 2 * mu * G[0][0];
-    rhs[1] = la * divv + 2 * mu * G[1][1];
-    rhs[2] = la * divv + 2 * mu * G[2][2];
-    rhs[3] = mu * (G[1][2] + G[2][1]);
-    rhs[4] = mu * (G[0][2] + G[2][0]);
-    rhs[5] = mu * (G[0][1] + G[1][0]);
-    if (e == es) {
-      const double w = s * A.src_vec[shot * Np + i];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) rhs[c] += (real)(w * spar[c]);
+    for (int l = 0; l < SP::VW; ++l) {
+      const real2v<real> o = update(b + l, qv[l], rv[u][l]);
+      nr[l] = o.r;
+      nq[l] = o.q;
     }
-    const int64_t base = (k0 + e) * 9 * Np + 3 * Np + i;
-    real qv[6], rold[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      qv[c] = qin[base + c * Np];
-      if (first)
-        rold[c] = (real)0;
-      else if constexpr (kStream)
-        rold[c] = __builtin_nontemporal_load(res + base + c * Np);
+    if constexpr (kStream) {
+      __builtin_nontemporal_store(nr, (typename SP::vec *)(rs + b));
+      if constexpr (sizeof(real) == 8)
+        __builtin_nontemporal_store(nq, (typename SP::vec *)(qo + b));
       else
-        rold[c] = res[base + c * Np];
+        *(typename SP::vec *)(qo + b) = nq;
+    } else {
+      *(typename SP::vec *)(rs + b) = nr;
+      *(typename SP::vec *)(qo + b) = nq;
     }
-    const real sg = (real)ssig[e];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      real r = rhs[c];
-      if (A.sponge) r -= sg * qv[c];
-      const real rn = first ? rdt * r : ra * rold[c] + rdt * r;
-      const real qn = qv[c] + rb * rn;
-      if constexpr (kStream) {
-        __builtin_nontemporal_store(rn, res + base + c * Np);
-        if constexpr (sizeof(real) == 8)
-          __builtin_nontemporal_store(qn, qout + base + c * Np);
-        else
-          qout[base + c * Np] = qn;
-      } else {
-        res[base + c * Np] = rn;
-        qout[base + c * Np] = qn;
-      }
-    }
+  }
+  if (tid < sp.hd) {
+    const real2v<real> o = update(tid, qh, rh);
+    rs[tid] = o.r;
+    qo[tid] = o.q;
+  }
+  if (tid < sp.tl) {
+    const real2v<real> o = update(tl0 + tid, qt, rt);
+    rs[tl0 + tid] = o.r;
+    qo[tl0 + tid] = o.q;
   }
 }
 

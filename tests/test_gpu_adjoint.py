@@ -206,29 +206,44 @@ def test_gradient_matches_central_differences():
 
 
 def test_full_size_gradient_matches_central_differences():
-    """The gradient workload at full size (6*16^3 = 24576 elements, order 3,
-    blob-perturbed starting medium), 300 steps with checkpoints every 100,
-    observed data zero (the misfit is then 1/2 dt sum trace^2, so no input
-    comes from the GPU path): GPU FP64 adjoint vs central differences of the
-    GPU forward on 3 seeded elements, relative error <= 1e-4."""
-    nsteps = 300
+    """The gradient workload at its stated size: 6*16^3 = 24576 elements,
+    order 3, blob-perturbed starting medium, 1500 steps, checkpoints every
+    100, observed data = the oracle's receiver traces of the true layered
+    medium over the same 1500 steps (stored by
+    tests/golden/make_long_window.py, with the time step used there).  GPU
+    FP64 adjoint vs central differences of the GPU FP64 forward (step 1e-6
+    relative) on 20 seeded elements (seed 52, among elements whose largest
+    gradient entry is >= 1e-3 of the global largest), all three parameters,
+    entries >= 1e-3 of the global largest: relative error <= 1e-4 each.
+    The FP32 gradient's error against the FP64 one is stated (<= 1e-3)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "c3_traces_1500steps.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden c3_traces_1500steps.npz not generated")
+    gold = np.load(path)
+    nsteps, dt, d = int(gold["steps"]), float(gold["dt"]), gold["traces"][None]
     ws = W.build_workload("c3_adjoint", medium="blob")
-    wt = W.build_workload("c3_adjoint")
     say("case full-size FD check K=%d steps=%d" % (ws["K"], nsteps))
-    s = gpu_solver(ws["mesh"], ws["N"], wt["rho"], wt["lam"], wt["mu"], 1.0)
-    dt = s.suggest_dt(wt["cfl"])                # fixed from the true medium
-    s.set_dt(dt)
-    s.set_material(ws["rho"], ws["lam"], ws["mu"])
-    s.set_source(0, ws["source"], ws["f0"], ws["t0"], ws["amp"])
-    s.set_receivers(0, ws["receivers"], nsteps)
-    d = np.zeros((1, len(ws["receivers"]), 3, nsteps))
-    s.zero_fields()
-    s.forward_checkpointed(nsteps, 100, d)
-    g = [x[0] for x in s.adjoint()]
+    grads = {}
+    for prec in (32, 64):
+        s = gpu_solver(ws["mesh"], ws["N"], ws["rho"], ws["lam"], ws["mu"], dt, prec)
+        s.set_source(0, ws["source"], ws["f0"], ws["t0"], ws["amp"])
+        s.set_receivers(0, ws["receivers"], nsteps)
+        s.zero_fields()
+        mis = s.forward_checkpointed(nsteps, 100, d)[0]
+        grads[prec] = [x[0] for x in s.adjoint()]
+        say("fp%d misfit %.6e" % (prec, mis))
+        if prec == 32:
+            s.close()
+    g = grads[64]
+    e32 = rel_l2(np.concatenate(grads[32]), np.concatenate(g))
+    say("fp32 gradient rel L2 vs fp64 %.3e" % e32)
+    assert e32 <= 1e-3
     gmax = max(np.abs(x).max() for x in g)
     assert gmax > 0
     eligible = np.nonzero(np.maximum.reduce([np.abs(x) for x in g]) >= 1e-3 * gmax)[0]
-    elems = np.random.default_rng(52).choice(eligible, size=3, replace=False)
+    elems = np.random.default_rng(52).choice(eligible, size=20, replace=False)
     base = [np.array(ws["rho"]), np.array(ws["lam"]), np.array(ws["mu"])]
     worst, n = 0.0, 0
     for k in elems:
@@ -244,10 +259,13 @@ def test_full_size_gradient_matches_central_differences():
                 s.zero_fields()
                 vals.append(s.forward_checkpointed(nsteps, nsteps, d)[0])
             fd = (vals[0] - vals[1]) / (2 * delta)
-            worst = max(worst, abs(fd - g[p][k]) / abs(fd))
+            err = abs(fd - g[p][k]) / abs(fd)
+            worst = max(worst, err)
             n += 1
-    say("full-size FD worst relative error %.2e over %d entries" % (worst, n))
-    assert n > 0 and worst <= 1e-4
+        say("  element %d done, worst so far %.2e over %d entries" % (k, worst, n))
+    say("full-size FD worst relative error %.2e over %d entries of %d elements"
+        % (worst, n, len(elems)))
+    assert n >= 20 and worst <= 1e-4
 
 
 def test_batched_gradients_of_uneven_lengths():

@@ -55,7 +55,7 @@ def test_c0_periodic_plane_wave_fp64():
 
 # stage kernel variants: 0 = one thread per node on the vector ALUs,
 # 1 = volume and lift as one GEMM on the matrix cores, 2 = the minimal-form
-# matrix-core kernel (orders 1-4 in FP64, 1-6 in FP32; 16 elements per
+# matrix-core kernel (orders 1-4 in FP64, 1-6 in FP32; 32 elements per
 # work-group, no persistent grid)
 KERNELS = (0, 1, 2)
 
@@ -143,7 +143,7 @@ def test_full_size_layered_fp64_bench_launch():
     w, dt, q0, q_ora, tr_ora = _full_c1_oracle()
     say("case full c1 fp64 K=%d" % w["K"])
     shapes = [(kv, be, wpc) for kv in (0, 1) for be in (7, 3)
-              for wpc in (0, 1, 2, 3, 4, 8, 16)] + [(2, 16, 0)]
+              for wpc in (0, 1, 2, 3, 4, 8, 16)] + [(2, 32, 0)]
     s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
     s.set_source(0, w["source"], w["f0"], 0.05, w["amp"])
     s.set_receivers(0, w["receivers"], 8)
@@ -166,7 +166,7 @@ def test_full_size_layered_fp32_bench_launch(kernel):
     s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt, 32)
     s.set_source(0, w["source"], w["f0"], 0.05, w["amp"])
     s.set_receivers(0, w["receivers"], 8)
-    for be in ((7, 3) if kernel < 2 else (16,)):
+    for be in ((7, 3) if kernel < 2 else (32,)):
         s.set_launch(kernel, be, 0)
         s.set_fields(0, q0)
         s.step(2)
@@ -333,7 +333,7 @@ def test_graph_replay_equals_eager_and_block_shapes_agree():
     souts = []
     for timing in (False, True):
         s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt)
-        s.set_launch(2, 16, 0)
+        s.set_launch(2, 32, 0)
         s.enable_timing(timing)
         s.set_source(0, w["source"], w["f0"], w["t0"], w["amp"])
         s.set_fields(0, q0)
@@ -342,7 +342,7 @@ def test_graph_replay_equals_eager_and_block_shapes_agree():
     assert np.array_equal(souts[0], souts[1])
     assert rel_l2(souts[0], outs[0]) <= FP64_TOL
     # a kernel variant or shape this build does not provide is refused
-    for bad in ((3, 0, 0), (0, 5, 0), (1, 5, 0), (0, 7, 65), (2, 7, 0), (2, 16, 2)):
+    for bad in ((3, 0, 0), (0, 5, 0), (1, 5, 0), (0, 7, 65), (2, 7, 0), (2, 32, 2)):
         with pytest.raises(DGWError) as ei:
             s.set_launch(*bad)
         assert ei.value.status == "DGW_EINVAL"

@@ -122,7 +122,7 @@ def test_full_size_general_mesh_fp64():
     s = gpu_solver(mesh, 4, rho, lam, mu, dt)
     s.set_source(0, src, 2.0, 0.05, 1.0, moment=MOMENT)
     s.set_receivers(0, rec, 8)
-    for shape in ((1, 7, 0), (1, 3, 0), (0, 7, 0), (0, 3, 0), (1, 7, 3), (2, 16, 0)):
+    for shape in ((1, 7, 0), (1, 3, 0), (0, 7, 0), (0, 3, 0), (1, 7, 3), (2, 32, 0)):
         s.set_launch(*shape)
         s.set_fields(0, q0)
         s.step(2)
