@@ -225,7 +225,7 @@ int dgw_adjoint(dgw_ctx *ctx, double *g_rho, double *g_lam, double *g_mu);
 /* State generation: a counter the context bumps on every call that changes
  * what a run computes (dgw_set_material, dgw_set_dt, dgw_set_source,
  * dgw_set_receivers, dgw_set_fields, dgw_set_damping, dgw_set_flux,
- * dgw_set_stiffness, and dgw_step when it advances a shot).
+ * dgw_set_stiffness, dgw_set_pml, and dgw_step when it advances a shot).
  * dgw_forward_checkpointed records the value it ends at, and dgw_adjoint
  * returns DGW_ESTATE when the counter has moved since, because the reverse
  * sweep reads the traces, material, time step and tables of the live
@@ -270,6 +270,40 @@ int dgw_set_flux(dgw_ctx *ctx, double tau);
  * dgw_adjoint includes it exactly.  Requires the mesh (DGW_ESTATE);
  * DGW_EINVAL for negative or non-finite rates. */
 int dgw_set_damping(dgw_ctx *ctx, const double *sigma);
+
+/* Convolutional perfectly matched layer (the recursive-convolution PML of
+ * Roden and Gedney, 2000, in the unsplit first-order form of Komatitsch and
+ * Martin, Geophysics 72, 2007, stretching factor 1).  In the layer every
+ * derivative d/dx_b gains a memory variable m, m_t = -(d_b + alpha_b) m -
+ * d_b du/dx_b: per node, phi_cb for D_cb = d sigma_cb / dx_b and psi_cb for
+ * G_cb = d v_c / dx_b (c, b = x, y, z), and the right-hand side gains
+ * (1/rho) sum_b phi_cb on v_c and lambda tr(Psi) I + mu (Psi + Psi^T) on
+ * sigma.  D and G are the scheme's own derivatives split by axis (volume part
+ * and the lifted flux-state change times n_b, the traction change dT extended
+ * to the symmetric stress change dT n^T + n dT^T - (n.dT) n n^T), so that
+ * with d = 0 the step is the plain scheme's.  Memory variables advance with
+ * the same LSERK4 stages.
+ *   n          layer elements (0 removes the layer; elements and profile
+ *              may then be NULL)
+ *   elements   [n] element ids, strictly increasing
+ *   profile    [n][6][Np] per node: d_x, d_y, d_z, alpha_x, alpha_y, alpha_z
+ *              (finite, >= 0; copied)
+ * Memory variables start at zero here and whenever dgw_set_fields sets a
+ * shot.  Isotropic elements only: DGW_ESTATE with a stiffness set (and
+ * dgw_set_stiffness refuses while a layer is set); dgw_forward_checkpointed
+ * and dgw_adjoint return DGW_ESTATE while a layer is set.  DGW_ERANGE for an
+ * element id out of range, DGW_EINVAL for unsorted ids or a negative or
+ * non-finite profile value.  Device memory: 2 x nshots x n x 18 x Np reals
+ * plus the profile. */
+int dgw_set_pml(dgw_ctx *ctx, int64_t n, const int32_t *elements, const double *profile);
+
+/* The layer's memory variables of one shot, out [n][18][Np] FP64 (phi_cb at
+ * 3 c + b, psi_cb at 9 + 3 c + b).  DGW_ESTATE without a layer. */
+int dgw_get_pml_memory(dgw_ctx *ctx, int shot, double *out);
+
+/* Average duration of the layer kernel launches of the last timed dgw_step
+ * (dgw_enable_timing), and how many were timed. */
+int dgw_pml_kernel_ms(dgw_ctx *ctx, double *ms, int64_t *launches);
 
 /* Anisotropic elements: per-element Voigt stiffness C [K][21], the upper
  * triangle row by row (C11 C12 .. C16 C22 .. C66) in the order xx, yy, zz,

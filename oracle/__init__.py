@@ -16,9 +16,11 @@ setup     connectivity, face node maps, affine geometry, point location
 solver    right-hand side, LSERK4, source, receivers, energy, misfit
 adjoint   discrete adjoint gradient (reverse mode through the discrete
           forward, with checkpointed recomputation)
+pml       convolutional perfectly matched layer (memory variables driven by
+          the scheme's directional derivatives)
 
 Every operator and formula here is stated in the docstrings of those modules;
 which statement pins which function is recorded in the tests.
 """
 
-from . import refelem, setup, solver, adjoint  # noqa: F401
+from . import refelem, setup, solver, adjoint, pml  # noqa: F401

@@ -197,41 +197,13 @@ def impedance(rho, C, Nm):
     return V @ torch.diag_embed(torch.sqrt(w)) @ V.transpose(-1, -2)
 
 
-def rhs(P, q, rho, lam, mu):
-    """L q for q [K, 9, Np] (no source); rho, lam, mu are [K] tensors
-    (lam and mu unused where P.stiffness is set)."""
+def face_states(P, q, rho, lam, mu):
+    """Changes of the flux states against the own trace on every face node:
+    dT = t* - t- and dV = v* - v- [K, 3, 4, Nfp] (upwind, blended or
+    anisotropic as set on P), and the outward normals n [K, 3, 4, 1]."""
     dt_ = q.dtype
-    Dr, Ds, Dt = P.Dr.to(dt_), P.Ds.to(dt_), P.Dt.to(dt_)
-    Xinv = P.Xinv.to(dt_)
-    # reference derivatives of every field, then physical ones:
-    # d/dx_b q_c = sum_r Xinv[r, b] (D_r q_c)
-    ref = torch.stack([q @ Dr.T, q @ Ds.T, q @ Dt.T], dim=2)       # [K,9,3,Np]
-    grad = torch.einsum("krb,kcrn->kcbn", Xinv, ref)              # [K,9,3,Np]
-    dx = lambda c, b: grad[:, c, b]
-    r = rho[:, None]
-    l = lam[:, None]
-    m = mu[:, None]
-    divv = dx(VX, 0) + dx(VY, 1) + dx(VZ, 2)
-    out = torch.stack([
-        (dx(SXX, 0) + dx(SXY, 1) + dx(SXZ, 2)) / r,
-        (dx(SXY, 0) + dx(SYY, 1) + dx(SYZ, 2)) / r,
-        (dx(SXZ, 0) + dx(SYZ, 1) + dx(SZZ, 2)) / r,
-        l * divv + 2.0 * m * dx(VX, 0),
-        l * divv + 2.0 * m * dx(VY, 1),
-        l * divv + 2.0 * m * dx(VZ, 2),
-        m * (dx(VY, 2) + dx(VZ, 1)),
-        m * (dx(VX, 2) + dx(VZ, 0)),
-        m * (dx(VX, 1) + dx(VY, 0)),
-    ], dim=1)                                                      # [K,9,Np]
-    C = P.stiffness
-    if C is not None:
-        strain = torch.stack([dx(VX, 0), dx(VY, 1), dx(VZ, 2), dx(VY, 2) + dx(VZ, 1),
-                              dx(VX, 2) + dx(VZ, 0), dx(VX, 1) + dx(VY, 0)], dim=1)
-        out = torch.cat([out[:, 0:3],
-                         torch.einsum("kij,kjn->kin", C.to(dt_), strain)], dim=1)
-
-    # ---- faces --------------------------------------------------------
     K, Nfp = P.K, P.Nfp
+    C = P.stiffness
     qm = q[:, :, P.Fmask].reshape(K, 9, 4, Nfp)
     qp = q[P.nb_elem, :, P.nb_node].permute(0, 3, 1, 2)            # [K,9,4,Nfp]
     zero = torch.zeros_like(qm)
@@ -303,6 +275,44 @@ def rhs(P, q, rho, lam, mu):
     vS = tau * vstar + (1.0 - tau) * 0.5 * (vm + vp)
     dT = tS - tm                                                   # [K,3,4,Nfp]
     dV = vS - vm
+    return dT, dV, n
+
+
+def rhs(P, q, rho, lam, mu):
+    """L q for q [K, 9, Np] (no source); rho, lam, mu are [K] tensors
+    (lam and mu unused where P.stiffness is set)."""
+    dt_ = q.dtype
+    Dr, Ds, Dt = P.Dr.to(dt_), P.Ds.to(dt_), P.Dt.to(dt_)
+    Xinv = P.Xinv.to(dt_)
+    # reference derivatives of every field, then physical ones:
+    # d/dx_b q_c = sum_r Xinv[r, b] (D_r q_c)
+    ref = torch.stack([q @ Dr.T, q @ Ds.T, q @ Dt.T], dim=2)       # [K,9,3,Np]
+    grad = torch.einsum("krb,kcrn->kcbn", Xinv, ref)              # [K,9,3,Np]
+    dx = lambda c, b: grad[:, c, b]
+    r = rho[:, None]
+    l = lam[:, None]
+    m = mu[:, None]
+    divv = dx(VX, 0) + dx(VY, 1) + dx(VZ, 2)
+    out = torch.stack([
+        (dx(SXX, 0) + dx(SXY, 1) + dx(SXZ, 2)) / r,
+        (dx(SXY, 0) + dx(SYY, 1) + dx(SYZ, 2)) / r,
+        (dx(SXZ, 0) + dx(SYZ, 1) + dx(SZZ, 2)) / r,
+        l * divv + 2.0 * m * dx(VX, 0),
+        l * divv + 2.0 * m * dx(VY, 1),
+        l * divv + 2.0 * m * dx(VZ, 2),
+        m * (dx(VY, 2) + dx(VZ, 1)),
+        m * (dx(VX, 2) + dx(VZ, 0)),
+        m * (dx(VX, 1) + dx(VY, 0)),
+    ], dim=1)                                                      # [K,9,Np]
+    C = P.stiffness
+    if C is not None:
+        strain = torch.stack([dx(VX, 0), dx(VY, 1), dx(VZ, 2), dx(VY, 2) + dx(VZ, 1),
+                              dx(VX, 2) + dx(VZ, 0), dx(VX, 1) + dx(VY, 0)], dim=1)
+        out = torch.cat([out[:, 0:3],
+                         torch.einsum("kij,kjn->kin", C.to(dt_), strain)], dim=1)
+
+    dT, dV, n = face_states(P, q, rho, lam, mu)
+    K, Nfp = P.K, P.Nfp
     ndv = (n * dV).sum(dim=1)                                      # [K,4,Nfp]
     lm = lam[:, None, None]
     mm = mu[:, None, None]

@@ -142,6 +142,8 @@ int dgw_forward_checkpointed(dgw_ctx *c, int64_t nsteps, int64_t every,
     return c->fail(DGW_ESTATE, "the adjoint supports the upwind flux only (flux weight 1)");
   if (c->have_aniso)
     return c->fail(DGW_ESTATE, "the adjoint supports isotropic elements only");
+  if (c->pml_n > 0)
+    return c->fail(DGW_ESTATE, "the adjoint does not support the perfectly matched layer");
   for (int64_t k = 0; k < c->mesh.K; ++k)
     if (c->mu[k] == 0.0)
       return c->fail(DGW_ESTATE, "the gradient is not defined with fluid (mu = 0) elements");
@@ -233,6 +235,8 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
     return c->fail(DGW_ESTATE, "the adjoint supports the upwind flux only (flux weight 1)");
   if (c->have_aniso)
     return c->fail(DGW_ESTATE, "the adjoint supports isotropic elements only");
+  if (c->pml_n > 0)
+    return c->fail(DGW_ESTATE, "the adjoint does not support the perfectly matched layer");
   if (!g_rho || !g_lam || !g_mu) return c->fail(DGW_EINVAL, "null gradient output");
   dgw_ctx::Adjoint *a = c->adj;
   int rc;

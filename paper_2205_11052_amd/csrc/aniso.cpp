@@ -274,6 +274,8 @@ extern "C" int dgw_set_stiffness(dgw_ctx *c, const double *C) {
     c->aniso_C.clear();
     return DGW_OK;
   }
+  if (c->pml_n > 0)
+    return c->fail(DGW_ESTATE, "the perfectly matched layer supports isotropic elements only");
   const int64_t K = c->mesh.K;
   for (int64_t i = 0; i < 21 * K; ++i)
     if (!std::isfinite(C[i]))

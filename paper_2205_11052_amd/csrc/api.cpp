@@ -8,6 +8,7 @@
 #include <limits>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/dgw.h"
@@ -381,6 +382,10 @@ int dgw_ctx::enqueue_step(int from, bool timed) {
       (void)hipEventRecord(ev_pool[ev_pool_used + 1], stream);
       ev_pool_used += 2;
     }
+    if (pml_n > 0) {
+      const int rc = enqueue_pml(d_q[from], d_q[1 - from], i, timed);
+      if (rc) return rc;
+    }
     from = 1 - from;
   }
   RecArgs r;
@@ -397,6 +402,75 @@ int dgw_ctx::enqueue_step(int from, bool timed) {
   r.shot_len = d_len;
   hipError_t e = launch_receivers(precision, nshots, r, stream);
   if (e != hipSuccess) return hipfail(e, "receiver kernel launch");
+  return DGW_OK;
+}
+
+// The layer's launch after stage `stage` (state `in` -> `out`).
+int dgw_ctx::enqueue_pml(const void *in, void *out, int stage, bool timed) {
+  const bool ev = timed && pml_ev_used + 2 <= (int)pml_ev.size();
+  if (ev) (void)hipEventRecord(pml_ev[pml_ev_used], stream);
+  auto fill = [&](auto &a) {
+    using real = std::remove_pointer_t<decltype(a.q_out)>;
+    a.q_in = (const real *)in;
+    a.q_out = (real *)out;
+    a.res = (real *)d_res;
+    a.mem = (real *)d_pml_mem;
+    a.mres = (real *)d_pml_mres;
+    a.elem = d_pml_elem;
+    a.prof = d_pml_prof;
+    a.meta = d_meta;
+    a.conn = d_conn;
+    a.nbnode = d_nbnode;
+    a.DrT = (const real *)d_DrT;
+    a.DsT = (const real *)d_DsT;
+    a.DtT = (const real *)d_DtT;
+    a.LIFTT = (const real *)d_LIFTT;
+    a.fmask = d_fmask;
+    a.nP = pml_n;
+    a.shot_stride = mesh.K * 9 * R.Np;
+    a.mem_stride = pml_n * 18 * R.Np;
+    a.shot_step = d_step;
+    a.shot_len = d_len;
+    a.ftau = (real)flux_tau;
+    a.rk_a = dgw::rk_a()[stage];
+    a.rk_b = dgw::rk_b()[stage];
+    a.dt = dt;
+  };
+  hipError_t e;
+  if (precision == 64) {
+    PmlArgs<double> a;
+    fill(a);
+    e = launch_pml(R.N, 64, nshots, &a, stream);
+  } else {
+    PmlArgs<float> a;
+    fill(a);
+    e = launch_pml(R.N, 32, nshots, &a, stream);
+  }
+  if (e != hipSuccess) return hipfail(e, "layer kernel launch");
+  if (ev) {
+    (void)hipEventRecord(pml_ev[pml_ev_used + 1], stream);
+    pml_ev_used += 2;
+  }
+  return DGW_OK;
+}
+
+void dgw_ctx::free_pml() {
+  dfree(d_pml_elem);
+  dfree(d_pml_prof);
+  dfree(d_pml_mem);
+  dfree(d_pml_mres);
+  d_pml_elem = nullptr;
+  d_pml_prof = nullptr;
+  d_pml_mem = d_pml_mres = nullptr;
+  pml_n = 0;
+}
+
+int dgw_ctx::clear_pml(int shot) {
+  if (pml_n == 0) return DGW_OK;
+  const size_t per = (size_t)pml_n * 18 * R.Np * real_size();
+  char *base = (char *)d_pml_mem + (shot < 0 ? 0 : shot * per);
+  hipError_t e = hipMemsetAsync(base, 0, shot < 0 ? per * nshots : per, stream);
+  if (e != hipSuccess) return hipfail(e, "hipMemsetAsync (layer memory)");
   return DGW_OK;
 }
 
@@ -470,6 +544,7 @@ void dgw_destroy(dgw_ctx *c) {
   c->free_adjoint();
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->adj_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->pml_ev) (void)hipEventDestroy(e);
   std::vector<void *> all = c->owned;
   for (void *p : all) c->dfree(p);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -666,6 +741,7 @@ int dgw_set_fields(dgw_ctx *c, int shot, const double *q) {
     rc = c->upload((float *)c->d_q[c->cur] + shot * n, tmp.data(), sizeof(float) * n);
   }
   if (rc) return rc;
+  if ((rc = c->clear_pml(shot))) return rc;
   c->loc[shot] = c->cur;
   c->h_step[shot] = 0;
   if ((rc = c->upload(c->d_step + shot, &c->h_step[shot], sizeof(int64_t)))) return rc;
@@ -718,6 +794,13 @@ int dgw_step(dgw_ctx *c, int64_t nsteps) {
       c->ev_pool.push_back(e);
     }
     c->ev_pool_used = 0;
+    const int pneed = c->pml_n > 0 ? need : 0;
+    while ((int)c->pml_ev.size() < pneed) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) break;
+      c->pml_ev.push_back(e);
+    }
+    c->pml_ev_used = 0;
   }
   int64_t done = 0;
   if (!timed && longest >= kGraphSteps) {
@@ -748,6 +831,14 @@ int dgw_step(dgw_ctx *c, int64_t nsteps) {
     }
     c->timed_launches = c->ev_pool_used / 2;
     c->timed_ms = c->timed_launches ? tot / c->timed_launches : 0.0;
+    double ptot = 0;
+    for (int i = 0; i + 1 < c->pml_ev_used; i += 2) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, c->pml_ev[i], c->pml_ev[i + 1]);
+      ptot += ms;
+    }
+    c->pml_timed = c->pml_ev_used / 2;
+    c->pml_ms = c->pml_timed ? ptot / c->pml_timed : 0.0;
   }
   return DGW_OK;
 }
@@ -888,6 +979,78 @@ int dgw_set_damping(dgw_ctx *c, const double *sigma) {
   int rc = c->upload(c->d_sponge, sigma, sizeof(double) * K);
   if (rc) return rc;
   c->have_sponge = true;
+  return DGW_OK;
+}
+
+int dgw_set_pml(dgw_ctx *c, int64_t n, const int32_t *elements, const double *profile) {
+  if (!c) return DGW_EINVAL;
+  if (!c->have_mesh) return c->fail(DGW_ESTATE, "set the mesh first");
+  if (n < 0) return c->fail(DGW_EINVAL, "negative layer element count");
+  const int64_t K = c->mesh.K;
+  const int Np = c->R.Np;
+  if (n > 0) {
+    if (c->have_aniso)
+      return c->fail(DGW_ESTATE, "the perfectly matched layer supports isotropic elements only");
+    if (!elements || !profile) return c->fail(DGW_EINVAL, "null layer elements or profile");
+    if (n > K) return c->fail(DGW_ERANGE, "more layer elements than elements");
+    for (int64_t p = 0; p < n; ++p) {
+      if (elements[p] < 0 || elements[p] >= K)
+        return c->fail(DGW_ERANGE, "layer element out of range at position " + std::to_string(p));
+      if (p > 0 && elements[p] <= elements[p - 1])
+        return c->fail(DGW_EINVAL, "layer elements must be strictly increasing");
+    }
+    for (int64_t i = 0; i < n * 6 * Np; ++i)
+      if (!std::isfinite(profile[i]) || profile[i] < 0)
+        return c->fail(DGW_EINVAL, "layer profile negative or not finite at layer element " +
+                                       std::to_string(i / (6 * Np)));
+  }
+  int rc;
+  if ((rc = c->ensure_device())) return rc;
+  c->invalidate_graph();
+  c->touch();
+  // the stream may still be running layer launches that read the old data
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return c->hipfail(e, "hipStreamSynchronize");
+  c->free_pml();
+  if (n == 0) return DGW_OK;
+  const size_t mbytes = (size_t)n * 18 * Np * c->real_size() * c->nshots;
+  c->d_pml_elem = (int32_t *)c->dalloc(sizeof(int32_t) * n);
+  c->d_pml_prof = (double *)c->dalloc(sizeof(double) * n * 6 * Np);
+  c->d_pml_mem = c->dalloc(mbytes);
+  c->d_pml_mres = c->dalloc(mbytes);
+  if (!c->d_pml_elem || !c->d_pml_prof || !c->d_pml_mem || !c->d_pml_mres) {
+    c->free_pml();
+    return c->fail(DGW_ENOMEM, "device allocation failed (layer)");
+  }
+  c->pml_n = n;
+  if ((rc = c->upload(c->d_pml_elem, elements, sizeof(int32_t) * n)) ||
+      (rc = c->upload(c->d_pml_prof, profile, sizeof(double) * n * 6 * Np)) ||
+      (rc = c->clear_pml(-1))) {
+    c->free_pml();
+    return rc;
+  }
+  return DGW_OK;
+}
+
+int dgw_get_pml_memory(dgw_ctx *c, int shot, double *out) {
+  if (!c) return DGW_EINVAL;
+  if (c->pml_n == 0) return c->fail(DGW_ESTATE, "no perfectly matched layer is set");
+  if (shot < 0 || shot >= c->nshots) return c->fail(DGW_ERANGE, "shot out of range");
+  if (!out) return c->fail(DGW_EINVAL, "null output");
+  const size_t n = (size_t)c->pml_n * 18 * c->R.Np;
+  if (c->precision == 64)
+    return c->download(out, (double *)c->d_pml_mem + shot * n, sizeof(double) * n);
+  std::vector<float> tmp(n);
+  int rc = c->download(tmp.data(), (float *)c->d_pml_mem + shot * n, sizeof(float) * n);
+  if (rc) return rc;
+  for (size_t i = 0; i < n; ++i) out[i] = tmp[i];
+  return DGW_OK;
+}
+
+int dgw_pml_kernel_ms(dgw_ctx *c, double *ms, int64_t *launches) {
+  if (!c || !ms || !launches) return DGW_EINVAL;
+  *ms = c->pml_ms;
+  *launches = c->pml_timed;
   return DGW_OK;
 }
 

@@ -42,6 +42,12 @@ struct dgw_ctx {
   double *d_aniso = nullptr;        // [K][DGW_ANI] anisotropic per-element data
   bool have_aniso = false;
   std::vector<double> rho, lam, mu;
+  // perfectly matched layer (pml.hip): its elements, per-node profile,
+  // memory variables and their stage residual (pml_n = 0: no layer)
+  int64_t pml_n = 0;
+  int32_t *d_pml_elem = nullptr;
+  double *d_pml_prof = nullptr;
+  void *d_pml_mem = nullptr, *d_pml_mres = nullptr;
 
   // device data
   double *d_meta = nullptr;
@@ -94,6 +100,11 @@ struct dgw_ctx {
   std::vector<hipEvent_t> adj_ev;
   double adj_ms = 0;
   int64_t adj_timed = 0;
+  // layer-kernel timing (dgw_step with timing on)
+  std::vector<hipEvent_t> pml_ev;
+  int pml_ev_used = 0;
+  double pml_ms = 0;
+  int64_t pml_timed = 0;
 
   // differentiation state (adjoint.cpp)
   struct Adjoint;
@@ -120,6 +131,9 @@ struct dgw_ctx {
   int aniso_table();                       // anisotropic per-element data
   double aniso_max_speed2(int64_t k) const;  // of an anisotropic element
   int enqueue_step(int from, bool timed);
+  int enqueue_pml(const void *in, void *out, int stage, bool timed);
+  void free_pml();
+  int clear_pml(int shot);                 // zero a shot's memory variables (-1: all)
   int build_graph();
   int gather_shots_to_cur(const std::vector<int64_t> &adv);
   void free_adjoint();

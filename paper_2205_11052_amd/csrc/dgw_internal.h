@@ -112,6 +112,35 @@ struct StageArgs {
   double rk_a, rk_b, rk_c, dt;
 };
 
+// Perfectly matched layer launch (pml.hip), after the stage kernel of the
+// same stage: the layer's nP elements `elem` (strictly increasing), their
+// per-node profile prof[p][6][Np] = (d_x, d_y, d_z, alpha_x, alpha_y,
+// alpha_z), memory variables mem[S][nP][18][Np] (phi_cb at 3 c + b, psi_cb
+// at 9 + 3 c + b) and their stage residual mres (same layout).
+template <typename real>
+struct PmlArgs {
+  const real *q_in;
+  real *q_out;
+  real *res;
+  real *mem, *mres;
+  const int32_t *elem;
+  const double *prof;
+  const double *meta;
+  const int32_t *conn;
+  const uint8_t *nbnode;
+  const real *DrT, *DsT, *DtT, *LIFTT;
+  const int32_t *fmask;
+  int64_t nP;
+  int64_t shot_stride;          // K * 9 * Np
+  int64_t mem_stride;           // nP * 18 * Np
+  const int64_t *shot_step;
+  const int64_t *shot_len;
+  real ftau;
+  double rk_a, rk_b, dt;
+};
+
+hipError_t launch_pml(int N, int precision, int nshots, const void *args, hipStream_t st);
+
 // A contiguous span of `cnt` values at element offset `off` of a
 // 16-byte-aligned array, split for 16-byte vector access: `hd` scalars up
 // to the first aligned address, `nv` vectors of VW values, `tl` scalars.

@@ -1,0 +1,272 @@
+// Convolutional perfectly matched layer (C-PML): the memory-variable update
+// and the layer's terms, launched after each stage kernel over the layer's
+// elements only.
+//
+// Model (Roden and Gedney 2000; Komatitsch and Martin, Geophysics 72, 2007,
+// unsplit first-order form with kappa = 1): in the layer every derivative
+// d/dx_b gains a memory variable m with m_t = -(d_b + alpha_b) m - d_b du/dx_b
+// (d_b, alpha_b >= 0 per node).  For the velocity-stress system the state
+// gains, per node, phi_cb (memory of D_cb = d sigma_cb / dx_b) and psi_cb
+// (memory of G_cb = d v_c / dx_b), and the right-hand side gains
+//   dL_v = (1/rho) sum_b phi_cb,  dL_sigma = lambda tr(Psi) I + mu (Psi + Psi^T).
+// D and G are the scheme's own derivatives split by axis: the volume part
+// sum_r Xinv[r][b] D_r u, and the face part Fscale n_b LIFT of the flux-state
+// change, with the traction change dT extended to the symmetric stress
+// change S = dT n^T + n dT^T - (n.dT) n n^T (S n = dT), so that summed over b
+// they give back the scheme's right-hand side.
+//
+// The stage kernel has already written res' = a res + dt (L q + s) and
+// q_out = q_in + b res'.  Adding the layer's terms to L q changes these to
+// res' + dt dL and q_out + b dt dL, which this kernel applies to the layer's
+// elements; it advances the memory variables with the same LSERK stage
+// (mres = a mres + dt m_t, m += b mres), all rates at the stage input.
+//
+// One thread per (layer element, node); the element's fields, per-element
+// data and the lifted face quantities are staged in LDS.
+
+#include "dgw_internal.h"
+#include "stage_common.h"
+
+namespace dgw {
+
+using stagec::Sz;
+
+namespace {
+
+constexpr int kPmlThreads = 256;
+
+template <int N>
+struct PmlSz {
+  static constexpr int Np = Sz<N>::Np;
+  // layer elements per work-group: a whole element's nodes per thread set
+  static constexpr int PB = (kPmlThreads / Np) < 32 ? (kPmlThreads / Np) : 32;
+};
+
+template <int N, typename real>
+__global__ void __launch_bounds__(kPmlThreads) pml_kernel(PmlArgs<real> A) {
+  constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Nfp;
+  constexpr int PB = PmlSz<N>::PB;
+  __shared__ real sq[PB * 9 * Np];
+  __shared__ real sfl[PB * NF * 6];
+  __shared__ double smeta[PB * DGW_META];
+  __shared__ int64_t sk[PB];
+  const int shot = blockIdx.y;
+  if (A.shot_step[shot] >= A.shot_len[shot]) return;   // uniform per work-group
+  const int64_t p0 = (int64_t)blockIdx.x * PB;
+  if (p0 >= A.nP) return;
+  const int nE = (int)((A.nP - p0) < PB ? (A.nP - p0) : PB);
+  const real *__restrict__ qin = A.q_in + shot * A.shot_stride;
+  real *__restrict__ qout = A.q_out + shot * A.shot_stride;
+  real *__restrict__ res = A.res + shot * A.shot_stride;
+  real *__restrict__ mem = A.mem + shot * A.mem_stride;
+  real *__restrict__ mres = A.mres + shot * A.mem_stride;
+  const int tid = threadIdx.x;
+
+  if (tid < nE) sk[tid] = A.elem[p0 + tid];
+  __syncthreads();
+  for (int t = tid; t < nE * 9 * Np; t += kPmlThreads) {
+    const int e = t / (9 * Np), r = t - e * 9 * Np;
+    sq[t] = qin[sk[e] * 9 * Np + r];
+  }
+  for (int t = tid; t < nE * DGW_META; t += kPmlThreads) {
+    const int e = t / DGW_META, r = t - e * DGW_META;
+    smeta[t] = A.meta[sk[e] * DGW_META + r];
+  }
+  __syncthreads();
+
+  // ---- faces: the flux-state changes, times Fscale ----
+  for (int t = tid; t < nE * NF; t += kPmlThreads) {
+    const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
+    const int64_t k = sk[e];
+    const double *g = smeta + e * DGW_META;
+    const real *qe = sq + e * 9 * Np;
+    const int n1 = A.fmask[fm];
+    real qm[9], p[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) qm[c] = qe[c * Np + n1];
+    const int cn = A.conn[k * 4 + f];
+    if (cn >= 0) {
+      const int64_t nb = (int64_t)(cn >> 5);
+      const int nn = A.nbnode[k * NF + fm];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) p[c] = qin[(nb * 9 + c) * Np + nn];
+    } else if (cn == CONN_FREE) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p[c] = qm[c];
+#pragma unroll
+      for (int c = 3; c < 9; ++c) p[c] = -qm[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) p[c] = (real)0;
+    }
+    const real nx = (real)g[M_NORMAL + 3 * f], ny = (real)g[M_NORMAL + 3 * f + 1],
+               nz = (real)g[M_NORMAL + 3 * f + 2];
+    const real dvx = p[0] - qm[0], dvy = p[1] - qm[1], dvz = p[2] - qm[2];
+    const real dsxx = p[3] - qm[3], dsyy = p[4] - qm[4], dszz = p[5] - qm[5];
+    const real dsyz = p[6] - qm[6], dsxz = p[7] - qm[7], dsxy = p[8] - qm[8];
+    const real dtx = dsxx * nx + dsxy * ny + dsxz * nz;
+    const real dty = dsxy * nx + dsyy * ny + dsyz * nz;
+    const real dtz = dsxz * nx + dsyz * ny + dszz * nz;
+    const real dvn = dvx * nx + dvy * ny + dvz * nz;
+    const real dtn = dtx * nx + dty * ny + dtz * nz;
+    const real zp = (real)g[M_ZP], zs = (real)g[M_ZS];
+    const real zpn = (real)g[M_ZPNB + f], zsn = (real)g[M_ZSNB + f];
+    const real izp = (real)g[M_IZPS + f], izs = (real)g[M_IZSS + f];
+    // the exact Riemann states' changes, blended with the central states'
+    // (half the jumps) by the upwind weight
+    const real kn = (dtn + zpn * dvn) * izp;
+    const real kTx = (dtx - dtn * nx + zsn * (dvx - dvn * nx)) * izs;
+    const real kTy = (dty - dtn * ny + zsn * (dvy - dvn * ny)) * izs;
+    const real kTz = (dtz - dtn * nz + zsn * (dvz - dvn * nz)) * izs;
+    const real tu = A.ftau, hc = ((real)1 - tu) * (real)0.5;
+    const real fs = (real)g[M_FSCALE + f];
+    real *d = sfl + (e * NF + fm) * 6;
+    d[0] = fs * (tu * (zp * kn * nx + zs * kTx) + hc * dtx);
+    d[1] = fs * (tu * (zp * kn * ny + zs * kTy) + hc * dty);
+    d[2] = fs * (tu * (zp * kn * nz + zs * kTz) + hc * dtz);
+    d[3] = fs * (tu * (kn * nx + kTx) + hc * dvx);
+    d[4] = fs * (tu * (kn * ny + kTy) + hc * dvy);
+    d[5] = fs * (tu * (kn * nz + kTz) + hc * dvz);
+  }
+  __syncthreads();
+
+  // ---- nodes: directional derivatives, layer terms, memory update ----
+  const int t = tid;
+  if (t >= nE * Np) return;
+  const int e = t / Np, i = t - e * Np;
+  const int64_t pi = p0 + e;
+  const int64_t k = sk[e];
+  const real *qe = sq + e * 9 * Np;
+  const double *g = smeta + e * DGW_META;
+  // the node's memory variables and profile: loads issued before the
+  // derivative loops so their latency is hidden
+  real mv[18];
+  const int64_t mb = pi * 18 * Np + i;
+#pragma unroll
+  for (int j = 0; j < 18; ++j) mv[j] = mem[mb + j * Np];
+  real db[3], ab[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    db[b] = (real)A.prof[(pi * 6 + b) * Np + i];
+    ab[b] = (real)A.prof[(pi * 6 + 3 + b) * Np + i];
+  }
+  real dr[9], ds[9], dtt[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) dr[c] = ds[c] = dtt[c] = (real)0;
+  for (int j = 0; j < Np; ++j) {
+    const real a0 = A.DrT[j * Np + i], a1 = A.DsT[j * Np + i], a2 = A.DtT[j * Np + i];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const real v = qe[c * Np + j];
+      dr[c] += a0 * v;
+      ds[c] += a1 * v;
+      dtt[c] += a2 * v;
+    }
+  }
+  real X[9];
+#pragma unroll
+  for (int u = 0; u < 9; ++u) X[u] = (real)g[M_XINV + u];
+  // sigma_cb in Voigt order (xx yy zz yz xz xy) as field index
+  constexpr int vo[3][3] = {{3, 8, 7}, {8, 4, 6}, {7, 6, 5}};
+  real Dd[3][3], Gd[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int s = vo[c][b];
+      Dd[c][b] = X[b] * dr[s] + X[3 + b] * ds[s] + X[6 + b] * dtt[s];
+      Gd[c][b] = X[b] * dr[c] + X[3 + b] * ds[c] + X[6 + b] * dtt[c];
+    }
+  const real *fle = sfl + e * NF * 6;
+  for (int f = 0; f < 4; ++f) {
+    real W[3] = {0, 0, 0}, U[3] = {0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < Nfp; ++m) {
+      const real l = A.LIFTT[(f * Nfp + m) * Np + i];
+      const real *s6 = fle + (f * Nfp + m) * 6;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        W[c] += l * s6[c];
+        U[c] += l * s6[3 + c];
+      }
+    }
+    const real n[3] = {(real)g[M_NORMAL + 3 * f], (real)g[M_NORMAL + 3 * f + 1],
+                       (real)g[M_NORMAL + 3 * f + 2]};
+    const real nW = n[0] * W[0] + n[1] * W[1] + n[2] * W[2];
+    // n is constant on the face, so the lift of n_b S_cb is
+    // n_b (W_c n_b + n_c W_b - n_c n_b (n.W)) with W the lifted dT
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        Dd[c][b] += n[b] * (W[c] * n[b] + n[c] * W[b] - n[c] * n[b] * nW);
+        Gd[c][b] += n[b] * U[c];
+      }
+  }
+  // layer terms of the stage input's memory variables
+  const real ri = (real)g[M_RHOINV], la = (real)g[M_LAM], mu = (real)g[M_MU];
+  real dl[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dl[c] = ri * (mv[3 * c] + mv[3 * c + 1] + mv[3 * c + 2]);
+  const real tr = mv[9] + mv[13] + mv[17];   // psi_xx + psi_yy + psi_zz
+  dl[3] = la * tr + 2 * mu * mv[9];
+  dl[4] = la * tr + 2 * mu * mv[13];
+  dl[5] = la * tr + 2 * mu * mv[17];
+  dl[6] = mu * (mv[9 + 5] + mv[9 + 7]);      // psi_yz + psi_zy
+  dl[7] = mu * (mv[9 + 2] + mv[9 + 6]);      // psi_xz + psi_zx
+  dl[8] = mu * (mv[9 + 1] + mv[9 + 3]);      // psi_xy + psi_yx
+  const real ra = (real)A.rk_a, rb = (real)A.rk_b, rdt = (real)A.dt;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const int64_t idx = (k * 9 + c) * Np + i;
+    const real add = rdt * dl[c];
+    res[idx] = res[idx] + add;
+    qout[idx] = qout[idx] + rb * add;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int jp = 3 * c + b, js = 9 + 3 * c + b;
+      const real rp = -(db[b] + ab[b]) * mv[jp] - db[b] * Dd[c][b];
+      const real rs = -(db[b] + ab[b]) * mv[js] - db[b] * Gd[c][b];
+      // stage 1 (a = 0) never reads mres, so stale values cannot leak in
+      const real np_ = (A.rk_a == 0.0) ? rdt * rp : ra * mres[mb + jp * Np] + rdt * rp;
+      const real ns_ = (A.rk_a == 0.0) ? rdt * rs : ra * mres[mb + js * Np] + rdt * rs;
+      mres[mb + jp * Np] = np_;
+      mres[mb + js * Np] = ns_;
+      mem[mb + jp * Np] = mv[jp] + rb * np_;
+      mem[mb + js * Np] = mv[js] + rb * ns_;
+    }
+}
+
+template <int N, typename real>
+hipError_t launch_n(const PmlArgs<real> &a, int nshots, hipStream_t st) {
+  constexpr int PB = PmlSz<N>::PB;
+  const dim3 grid((unsigned)((a.nP + PB - 1) / PB), (unsigned)nshots);
+  hipLaunchKernelGGL((pml_kernel<N, real>), grid, dim3(kPmlThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_t(int N, const PmlArgs<real> &a, int nshots, hipStream_t st) {
+  switch (N) {
+    case 1: return launch_n<1, real>(a, nshots, st);
+    case 2: return launch_n<2, real>(a, nshots, st);
+    case 3: return launch_n<3, real>(a, nshots, st);
+    case 4: return launch_n<4, real>(a, nshots, st);
+    case 5: return launch_n<5, real>(a, nshots, st);
+    case 6: return launch_n<6, real>(a, nshots, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_pml(int N, int precision, int nshots, const void *args, hipStream_t st) {
+  if (precision == 64)
+    return launch_t<double>(N, *(const PmlArgs<double> *)args, nshots, st);
+  return launch_t<float>(N, *(const PmlArgs<float> *)args, nshots, st);
+}
+
+}  // namespace dgw

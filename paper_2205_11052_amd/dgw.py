@@ -143,6 +143,7 @@ class Solver:
         if torch_allocator:
             self._use_torch_allocator()
         self.Np = (order + 1) * (order + 2) * (order + 3) // 6
+        self.pml_n = 0
         self.Nfp = (order + 1) * (order + 2) // 2
         self.K = 0
         self.nrec = [0] * nshots
@@ -345,6 +346,37 @@ class Solver:
             return
         sg = self._per_element(sigma, 1, "sigma")
         self._check(self.lib.dgw_set_damping(self._ctx, _dptr(sg)), "dgw_set_damping")
+
+    def set_pml(self, elements=None, profile=None):
+        """Convolutional perfectly matched layer on the listed elements
+        (strictly increasing ids) with the per-node profile [n, 6, Np]
+        (d_x, d_y, d_z, alpha_x, alpha_y, alpha_z); None removes it."""
+        if elements is None:
+            self._check(self.lib.dgw_set_pml(self._ctx, 0, None, None), "dgw_set_pml")
+            self.pml_n = 0
+            return
+        el = np.ascontiguousarray(elements, dtype=np.int32)
+        pr = np.ascontiguousarray(profile, dtype=np.float64)
+        if el.ndim != 1 or pr.shape != (el.shape[0], 6, self.Np):
+            raise ValueError("elements must be [n] and profile [n, 6, Np]")
+        self._check(self.lib.dgw_set_pml(
+            self._ctx, el.shape[0], el.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(pr)),
+            "dgw_set_pml")
+        self.pml_n = el.shape[0]
+
+    def pml_memory(self, shot=0):
+        """The layer's memory variables of a shot, [n, 18, Np]."""
+        out = np.empty((self.pml_n, 18, self.Np))
+        self._check(self.lib.dgw_get_pml_memory(self._ctx, int(shot), _dptr(out)),
+                    "dgw_get_pml_memory")
+        return out
+
+    def pml_kernel_ms(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(self.lib.dgw_pml_kernel_ms(self._ctx, C.byref(ms), C.byref(n)),
+                    "dgw_pml_kernel_ms")
+        return ms.value, n.value
 
     def set_stiffness(self, C=None):
         """Anisotropic elements: Voigt stiffness per element, [K, 6, 6]

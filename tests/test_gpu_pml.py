@@ -1,0 +1,229 @@
+"""The convolutional perfectly matched layer (dgw_set_pml) on the GPU against
+the oracle with the same per-node profile: fields, receiver traces and the
+layer's memory variables, FP64 relative L2 <= 1e-12, FP32 <= 1e-5, with each
+stage kernel as the main kernel, the blended flux, a sponge on top, fluid
+elements in the layer, a moment source and two shots; the full-size
+82944-element order-4 workload in the benchmark's launch shapes; a zero
+profile and a removed layer give the plain run bit for bit; setting a shot's
+fields restarts its memory variables; arguments are checked.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import pml as OP
+from paper_2205_11052_amd.dgw import DGWError
+from gpu_helpers import (gpu_solver, oracle_problem, rel_l2, random_fields, say)
+
+pytestmark = pytest.mark.gpu
+
+MOMENT = (1.0, -0.5, 0.25, 0.3, -0.2, 0.1)
+
+
+def _random_medium(K, seed, fluid=0):
+    rng = np.random.default_rng(seed)
+    cp = rng.uniform(1.5, 3.0, K)
+    cs = cp / rng.uniform(1.5, 2.2, K)
+    rho = rng.uniform(1.0, 3.0, K)
+    if fluid:
+        cs[rng.choice(K, fluid, replace=False)] = 0.0
+    return W.lame_from_velocities(cp, cs, rho)
+
+
+def _unit_layer(mesh, N, width=0.3):
+    return W.pml_layer(mesh, N, hi=(1.0, 1.0, 1.0), width=width, cp_max=3.0,
+                       reflection=1e-3, f0=2.0)
+
+
+def _oracle(P, q0, rho, lam, mu, d, a, dt, nsteps):
+    t = lambda x: torch.as_tensor(np.asarray(x, dtype=np.float64))
+    q, m, tr = OP.run(P, t(q0).clone(), t(rho), t(lam), t(mu), t(d), t(a), dt, nsteps,
+                      record=P.receivers is not None)
+    return q.numpy(), m.numpy(), (tr.numpy() if tr is not None else None)
+
+
+@pytest.mark.parametrize("N,kernel,prec,tau,extra", [
+    (2, 0, 64, 1.0, ""), (3, 0, 64, 1.0, ""), (3, 1, 64, 1.0, ""), (3, 2, 64, 1.0, ""),
+    (4, 0, 64, 1.0, ""), (4, 1, 64, 1.0, ""), (4, 2, 64, 1.0, ""),
+    (4, 1, 64, 0.5, ""), (4, 1, 64, 1.0, "sponge"), (3, 1, 64, 1.0, "fluid"),
+    (1, 0, 64, 1.0, ""), (5, 1, 64, 1.0, ""), (6, 0, 64, 1.0, ""),
+    (4, 0, 32, 1.0, ""), (4, 1, 32, 1.0, ""), (4, 2, 32, 1.0, "")])
+def test_pml_matches_oracle(N, kernel, prec, tau, extra):
+    mesh = W.kuhn_cube(3, 1.0)
+    K = mesh["etov"].shape[0]
+    elems, prof, d, a = _unit_layer(mesh, N)
+    say("case pml N=%d kernel=%d fp%d tau=%.1f %s K=%d layer=%d"
+        % (N, kernel, prec, tau, extra, K, len(elems)))
+    assert 0 < len(elems) < K
+    rho, lam, mu = _random_medium(K, 30 + N, fluid=12 if extra == "fluid" else 0)
+    P = oracle_problem(mesh, N)
+    P.flux_tau = tau
+    sig = None
+    if extra == "sponge":
+        sig = W.sponge_profile(W.element_centroids(mesh), hi=(1.0, 1.0, 1.0),
+                               width=0.4, sigma_max=3.0)
+        P.sponge = torch.as_tensor(sig)
+    dt = P.suggest_dt(rho, lam, mu, 0.5)
+    q0 = random_fields(K, P.Np, 40 + N)
+    src = np.array([0.37, 0.52, 0.61])
+    rec = np.array([[0.2, 0.3, 1.0], [0.8, 0.6, 0.5], [0.05, 0.5, 0.5]])
+    P.set_source(src, 3.0, 0.1, 2.0, moment=MOMENT)
+    P.set_receivers(rec)
+    s = gpu_solver(mesh, N, rho, lam, mu, dt, precision=prec, kernel=kernel)
+    s.set_flux(tau)
+    if sig is not None:
+        s.set_damping(sig)
+    s.set_pml(elems, prof)
+    s.set_source(0, src, 3.0, 0.1, 2.0, moment=MOMENT)
+    s.set_receivers(0, rec, 16)
+    s.set_fields(0, q0)
+    nst = 7
+    s.step(nst)
+    q_o, m_o, tr_o = _oracle(P, q0, rho, lam, mu, d, a, dt, nst)
+    err = rel_l2(s.get_fields(0), q_o)
+    terr = rel_l2(s.read_traces(0), tr_o)
+    merr = rel_l2(s.pml_memory(0), m_o[elems])
+    say("pml fields %.3e traces %.3e memory %.3e" % (err, terr, merr))
+    tol = 1e-12 if prec == 64 else 1e-5
+    assert err <= tol and terr <= tol and merr <= tol
+    # the memory variables outside the layer stay zero in the oracle
+    out = np.setdiff1d(np.arange(K), elems)
+    assert np.array_equal(m_o[out], np.zeros_like(m_o[out]))
+    assert np.abs(m_o[elems]).max() > 0
+    if prec == 64:
+        # the layer is visible: the plain run differs
+        zero = np.zeros_like(d)
+        q_plain, _, _ = _oracle(P, q0, rho, lam, mu, zero, zero, dt, nst)
+        assert rel_l2(q_plain, q_o) > 1e3 * tol
+    s.close()
+
+
+def test_pml_two_shots():
+    mesh = W.kuhn_cube(3, 1.0)
+    K = mesh["etov"].shape[0]
+    N = 3
+    elems, prof, d, a = _unit_layer(mesh, N)
+    rho, lam, mu = _random_medium(K, 5)
+    P = oracle_problem(mesh, N)
+    dt = P.suggest_dt(rho, lam, mu, 0.5)
+    s = gpu_solver(mesh, N, rho, lam, mu, dt, nshots=2, kernel=1)
+    s.set_pml(elems, prof)
+    q0 = [random_fields(K, P.Np, 60 + i) for i in range(2)]
+    for i in range(2):
+        s.set_fields(i, q0[i])
+    s.step(6)
+    for i in range(2):
+        q_o, m_o, _ = _oracle(P, q0[i], rho, lam, mu, d, a, dt, 6)
+        err = rel_l2(s.get_fields(i), q_o)
+        merr = rel_l2(s.pml_memory(i), m_o[elems])
+        say("pml shot %d fields %.3e memory %.3e" % (i, err, merr))
+        assert err <= 1e-12 and merr <= 1e-12
+    s.close()
+
+
+def test_full_size_pml_fp64():
+    """The 82944-element order-4 layered workload with a layer one unit thick
+    on the five absorbing sides, random fields, one step against the oracle
+    in the benchmark's launch shapes."""
+    w = W.build_workload("c1_layered_n24")
+    cp_max = float(np.sqrt((w["lam"] + 2 * w["mu"]) / w["rho"]).max())
+    elems, prof, d, a = W.pml_layer(w["mesh"], w["N"], width=1.0, cp_max=cp_max,
+                                    reflection=1e-3, f0=w["f0"])
+    say("case full pml K=%d layer=%d" % (w["K"], len(elems)))
+    P = oracle_problem(w["mesh"], w["N"])
+    rho, lam, mu = w["rho"], w["lam"], w["mu"]
+    dt = P.suggest_dt(rho, lam, mu, w["cfl"])
+    q0 = random_fields(w["K"], P.Np, 15)
+    q_o, m_o, _ = _oracle(P, q0, rho, lam, mu, d, a, dt, 1)
+    s = gpu_solver(w["mesh"], w["N"], rho, lam, mu, dt)
+    s.set_pml(elems, prof)
+    for shape in ((1, 7, 0), (0, 7, 0), (2, 32, 0)):
+        s.set_launch(*shape)
+        s.set_fields(0, q0)
+        s.step(1)
+        err = rel_l2(s.get_fields(0), q_o)
+        merr = rel_l2(s.pml_memory(0), m_o[elems])
+        say("full pml shape %s fields %.3e memory %.3e" % (shape, err, merr))
+        assert err <= 1e-12 and merr <= 1e-12
+    s.close()
+
+
+def test_zero_profile_and_removed_layer_give_the_plain_run():
+    mesh = W.kuhn_cube(2, 1.0)
+    K = mesh["etov"].shape[0]
+    rho, lam, mu = _random_medium(K, 7)
+    q0 = random_fields(K, 35, 8)
+    elems, prof, _, _ = _unit_layer(mesh, 4, width=0.4)
+    out = []
+    for mode in ("plain", "zero", "removed"):
+        s = gpu_solver(mesh, 4, rho, lam, mu, 1e-3, kernel=1)
+        if mode == "zero":
+            s.set_pml(elems, np.zeros_like(prof))
+        if mode == "removed":
+            s.set_pml(elems, prof)
+            s.set_fields(0, q0)
+            s.step(3)
+            s.set_pml(None)
+        s.set_fields(0, q0)
+        s.step(5)
+        out.append(s.get_fields(0))
+        if mode == "zero":
+            assert not s.pml_memory(0).any()
+        s.close()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+def test_set_fields_restarts_the_memory_variables():
+    mesh = W.kuhn_cube(2, 1.0)
+    K = mesh["etov"].shape[0]
+    rho, lam, mu = _random_medium(K, 9)
+    q0 = random_fields(K, 20, 10)
+    elems, prof, _, _ = _unit_layer(mesh, 3, width=0.4)
+    s = gpu_solver(mesh, 3, rho, lam, mu, 1e-3, kernel=0)
+    s.set_pml(elems, prof)
+    s.set_fields(0, q0)
+    s.step(4)
+    first, mem1 = s.get_fields(0), s.pml_memory(0)
+    assert np.abs(mem1).max() > 0
+    s.set_fields(0, random_fields(K, 20, 11))
+    assert not s.pml_memory(0).any()
+    s.step(2)
+    s.set_fields(0, q0)
+    s.step(4)
+    assert np.array_equal(s.get_fields(0), first)
+    assert np.array_equal(s.pml_memory(0), mem1)
+    s.close()
+
+
+def test_pml_arguments_checked():
+    mesh = W.kuhn_cube(2, 1.0)
+    K = mesh["etov"].shape[0]
+    rho, lam, mu = _random_medium(K, 1)
+    elems, prof, _, _ = _unit_layer(mesh, 2, width=0.4)
+    s = gpu_solver(mesh, 2, rho, lam, mu, 1e-3)
+
+    def code(fn):
+        with pytest.raises(DGWError) as e:
+            fn()
+        return e.value.code
+
+    assert code(lambda: s.set_pml(elems[::-1].copy(), prof)) == -1       # unsorted
+    bad = elems.copy()
+    bad[-1] = K
+    assert code(lambda: s.set_pml(bad, prof)) == -6                       # out of range
+    for v in (-1.0, np.nan, np.inf):
+        p = prof.copy()
+        p[1, 2, 3] = v
+        assert code(lambda: s.set_pml(elems, p)) == -1
+    s.set_pml(elems, prof)
+    C = W.isotropic_stiffness(lam, mu)
+    assert code(lambda: s.set_stiffness(C)) == -5
+    s.set_receivers(0, np.array([[0.5, 0.5, 0.5]]), 4)
+    s.zero_fields()
+    assert code(lambda: s.forward_checkpointed(4, 2, np.zeros((1, 1, 3, 4)))) == -5
+    s.set_pml(None)
+    s.set_stiffness(C)
+    assert code(lambda: s.set_pml(elems, prof)) == -5
+    s.close()

@@ -95,6 +95,46 @@ def sponge_profile(centroids, lo=(0.0, 0.0, 0.0), hi=(BOX, BOX, BOX), width=1.0,
     return sigma_max * s * s
 
 
+def pml_profile(points, lo=(0.0, 0.0, 0.0), hi=(BOX, BOX, BOX), width=1.0,
+                cp_max=4.2, reflection=1e-3, f0=1.0,
+                faces=("x-", "x+", "y-", "y+", "z-")):
+    """Per-axis damping profiles of a convolutional perfectly matched layer
+    of the given width inside the box [lo, hi] along the listed faces, at
+    points [..., 3] (element centroids or nodes): for axis b,
+    r_b = (depth into the layer along b) / width in [0, 1], d_b = d0 r_b^2 with
+    d0 = 3 cp_max ln(1 / reflection) / (2 width) (the quadratic profile's
+    nominal normal-incidence reflection), and the frequency shift
+    alpha_b = pi f0 (1 - r_b) inside the layer, 0 outside.  Returns
+    (d [..., 3], alpha [..., 3])."""
+    c = np.asarray(points, dtype=np.float64)
+    r = np.zeros_like(c)
+    for f in faces:
+        a = "xyz".index(f[0])
+        depth = width - (c[..., a] - lo[a] if f[1] == "-" else hi[a] - c[..., a])
+        r[..., a] = np.maximum(r[..., a], np.clip(depth / width, 0.0, 1.0))
+    d0 = 3.0 * cp_max * np.log(1.0 / reflection) / (2.0 * width)
+    d = d0 * r * r
+    alpha = np.where(r > 0, np.pi * f0 * (1.0 - r), 0.0)
+    return d, alpha
+
+
+def pml_layer(mesh, N, **kw):
+    """The perfectly matched layer of ``pml_profile`` (same keywords) at the
+    nodes of an order-N mesh, in the two forms the solvers take: per node for
+    every element, d [K, 3, Np] and alpha [K, 3, Np], and restricted to the
+    layer, the strictly increasing ids of the elements with d > 0 at some
+    node and their profile [n, 6, Np] (d_x, d_y, d_z, alpha_x, alpha_y,
+    alpha_z).  Returns (elements, profile, d, alpha)."""
+    from .mesh import lattice_node_coords
+    X = lattice_node_coords(mesh, N)                               # [K, Np, 3]
+    d, a = pml_profile(X, **kw)
+    d = np.ascontiguousarray(np.moveaxis(d, 2, 1))
+    a = np.ascontiguousarray(np.moveaxis(a, 2, 1))
+    elems = np.nonzero((d > 0).any(axis=(1, 2)))[0].astype(np.int32)
+    prof = np.ascontiguousarray(np.concatenate([d[elems], a[elems]], axis=1))
+    return elems, prof, d, a
+
+
 def isotropic_stiffness(lam, mu):
     """Voigt stiffness [K, 6, 6] (order xx, yy, zz, yz, xz, xy; engineering
     shear strains) of isotropic elements."""

@@ -95,6 +95,67 @@ def kuhn_cube(n, L=1.0, periodic=False, top_free_surface=True):
             "face_bc": face_bc, "n": n, "L": float(L), "h": h}
 
 
+def kuhn_box(nx, ny, nz, Lx, Ly, Lz, periodic=(False, False, False), free_faces=()):
+    """The Kuhn split of the box [0, Lx] x [0, Ly] x [0, Lz] cut into
+    nx x ny x nz cells (the same six tetrahedra per cell as ``kuhn_cube``,
+    cell c = i + nx (j + ny k), tetrahedron 6 c + p).  ``periodic`` marks the
+    axes whose opposite faces are identified (each needs at least 3 cells);
+    boundary faces on the box faces listed in ``free_faces`` ("x-" is x = 0,
+    "z+" is z = Lz, ...) are free surfaces, every other boundary face is
+    absorbing.  Same keys as ``kuhn_cube`` plus ``shape`` and ``lengths``."""
+    n = np.array([nx, ny, nz], dtype=np.int64)
+    Ls = np.array([Lx, Ly, Lz], dtype=np.float64)
+    m = n + 1
+    ii, jj, kk = np.meshgrid(np.arange(m[0]), np.arange(m[1]), np.arange(m[2]),
+                             indexing="ij")
+    vid = lambda i, j, k: i + m[0] * (j + m[1] * k)
+    nvert = int(m.prod())
+    vxyz = np.empty((nvert, 3), dtype=np.float64)
+    idx = vid(ii, jj, kk).ravel()
+    h = Ls / n
+    vxyz[idx, 0] = ii.ravel() * h[0]
+    vxyz[idx, 1] = jj.ravel() * h[1]
+    vxyz[idx, 2] = kk.ravel() * h[2]
+    K = int(6 * n.prod())
+    etov = np.empty((K, 4), dtype=np.int64)
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                cell = i + nx * (j + ny * k)
+                for p, perm in enumerate(_PERMS):
+                    pos = np.array([i, j, k])
+                    verts = [vid(*pos)]
+                    for ax in perm:
+                        pos = pos.copy()
+                        pos[ax] += 1
+                        verts.append(vid(*pos))
+                    etov[6 * cell + p] = verts
+    a = vxyz[etov[:, 1]] - vxyz[etov[:, 0]]
+    b = vxyz[etov[:, 2]] - vxyz[etov[:, 0]]
+    d = vxyz[etov[:, 3]] - vxyz[etov[:, 0]]
+    det = np.einsum("ki,ki->k", a, np.cross(b, d))
+    neg = det < 0
+    etov[neg, 2], etov[neg, 3] = etov[neg, 3].copy(), etov[neg, 2].copy()
+    pid = None
+    if any(periodic):
+        wrap = [np.mod(g, n[a_]) if periodic[a_] else g
+                for a_, g in enumerate((ii, jj, kk))]
+        p_ = wrap[0] + m[0] * (wrap[1] + m[1] * wrap[2])
+        pid = np.empty(nvert, dtype=np.int32)
+        pid[idx] = p_.ravel()
+    face_bc = np.full((K, 4), BC_ABSORBING, dtype=np.int8)
+    for name in free_faces:
+        ax = "xyz".index(name[0])
+        at = 0.0 if name[1] == "-" else Ls[ax]
+        for f in range(4):
+            fv = vxyz[etov[:, [a_ for a_ in range(4) if a_ != f]]]   # [K, 3, 3]
+            on = np.all(np.isclose(fv[:, :, ax], at, rtol=0, atol=1e-12 * Ls[ax]), axis=1)
+            face_bc[on, f] = BC_FREE_SURFACE
+    return {"vxyz": vxyz, "etov": etov.astype(np.int32), "vertex_periodic_id": pid,
+            "face_bc": face_bc, "shape": (nx, ny, nz), "lengths": (Lx, Ly, Lz),
+            "h": float(h.min())}
+
+
 # the 12 even permutations of (0, 1, 2, 3): relabelling an element's vertices
 # by one of them keeps its orientation positive
 EVEN_PERMS = [p for p in
