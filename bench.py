@@ -422,26 +422,47 @@ def general_mesh_form(torch, stream, w, steps, warmup, structured_ms):
     return out
 
 
+def pml_bytes(n, Np, real_bytes):
+    """Algorithmic bytes of one layer-kernel launch over n layer elements:
+    the stage input read once (9 Np), the residual and output state read and
+    written (4 x 9 Np), the memory variables and their residual read and
+    written (4 x 18 Np), the per-node profile (6 Np, FP64) and the
+    per-element data (DGW_META doubles); neighbour traces are not counted."""
+    return n * (real_bytes * Np * (9 + 36 + 72) + 8 * 6 * Np + META_BYTES)
+
+
 def variants_form(torch, stream, w, steps, warmup, plain_ms):
     """Method variants on the workload's mesh (82944 elements, order 4,
     FP64), each with the launch shape the autotuner picks for it: the
     layered medium with an absorbing sponge one unit thick on the five
-    absorbing sides, and a fully anisotropic heterogeneous medium (seeded
+    absorbing sides; the same medium with a convolutional perfectly matched
+    layer of the same width (quadratic profile, nominal reflection 1e-3,
+    frequency shift pi f0), whose kernel runs after each stage over the
+    layer's elements; and a fully anisotropic heterogeneous medium (seeded
     random stiffness per element; node-per-thread form).  Algorithmic bytes
     add the per-element anisotropic data (DGW_ANI doubles) read once."""
     import workloads as W
     K, Np = w["K"], 35
     cen = W.element_centroids(w["mesh"])
     out = {}
-    for name in ("sponge", "anisotropic"):
+    for name in ("sponge", "pml", "anisotropic"):
+        progress("variant %s" % name)
         with torch.cuda.stream(stream):
             from paper_2205_11052_amd import Solver
             s = Solver(w["N"], 64, 1, stream=stream.cuda_stream)
             s.set_mesh_dict(w["mesh"])
             extra = 0
+            nlayer = 0
             if name == "sponge":
                 s.set_material(w["rho"], w["lam"], w["mu"])
                 s.set_damping(W.sponge_profile(cen, width=1.0, sigma_max=3.0))
+            elif name == "pml":
+                s.set_material(w["rho"], w["lam"], w["mu"])
+                cp_max = float(np.sqrt((w["lam"] + 2 * w["mu"]) / w["rho"]).max())
+                el, prof, _, _ = W.pml_layer(w["mesh"], w["N"], width=1.0, cp_max=cp_max,
+                                             reflection=1e-3, f0=w["f0"])
+                s.set_pml(el, prof)
+                nlayer = len(el)
             else:
                 rho, C = W.random_stiffness(K, 2205)
                 s.set_material(rho, np.ones(K), np.ones(K))
@@ -453,14 +474,22 @@ def variants_form(torch, stream, w, steps, warmup, plain_ms):
             shape = s.autotune()
             sec, _ = timed_steps(torch, s, stream, steps, warmup)
             kms, _ = kernel_avg_ms(s)
+            pms = s.pml_kernel_ms()[0] if nlayer else 0.0
             s.close()
         out[name] = {
             "value": round(9 * Np * K * 5 * steps / sec / 1e9, 3),
+            "ms_per_step": round(sec / steps * 1e3, 4),
             "kernel_avg_ms": round(kms, 5),
             "hbm_frac": round((stage_bytes(K, Np, 8) + extra) / (kms / 1e3) / 1e9
                               / HBM_PEAK_GBS, 4),
             "vs_plain": round(plain_ms / kms, 3),
             "launch_shape": list(shape)}
+        if nlayer:
+            out[name].update({
+                "layer_elements": nlayer,
+                "layer_kernel_avg_ms": round(pms, 5),
+                "layer_kernel_hbm_frac": round(pml_bytes(nlayer, Np, 8) / (pms / 1e3) / 1e9
+                                               / HBM_PEAK_GBS, 4)})
     return out
 
 
@@ -523,13 +552,13 @@ def batched_gradients_form(torch, stream, w, nshots=8, ckpt=100, t0=0.1):
             s = make(prec, wb, dt)
             s.zero_fields()
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
+            tstart = time.perf_counter()
             mis = s.forward_checkpointed(nsteps, ckpt, d)
             progress("batched gradients fp%d: forward with checkpoints done" % prec)
             g = s.adjoint()
             progress("batched gradients fp%d: reverse sweep done" % prec)
             torch.cuda.synchronize()
-            sec = time.perf_counter() - t0
+            sec = time.perf_counter() - tstart
             s.close()
             torch.cuda.empty_cache()      # the FP64 batch needs ~210 GB
             grads[prec] = g

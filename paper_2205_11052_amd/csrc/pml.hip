@@ -21,8 +21,9 @@
 // elements; it advances the memory variables with the same LSERK stage
 // (mres = a mres + dt m_t, m += b mres), all rates at the stage input.
 //
-// One thread per (layer element, node); the element's fields, per-element
-// data and the lifted face quantities are staged in LDS.
+// Two threads per (layer element, node), one for each half of the memory
+// variables; the element's fields, per-element data and the lifted face
+// quantities are staged in LDS.
 
 #include "dgw_internal.h"
 #include "stage_common.h"
@@ -38,8 +39,8 @@ constexpr int kPmlThreads = 256;
 template <int N>
 struct PmlSz {
   static constexpr int Np = Sz<N>::Np;
-  // layer elements per work-group: a whole element's nodes per thread set
-  static constexpr int PB = (kPmlThreads / Np) < 32 ? (kPmlThreads / Np) : 32;
+  // layer elements per work-group: two threads per node
+  static constexpr int PB = (kPmlThreads / (2 * Np)) < 32 ? (kPmlThreads / (2 * Np)) : 32;
 };
 
 template <int N, typename real>
@@ -131,112 +132,148 @@ __global__ void __launch_bounds__(kPmlThreads) pml_kernel(PmlArgs<real> A) {
   __syncthreads();
 
   // ---- nodes: directional derivatives, layer terms, memory update ----
-  const int t = tid;
-  if (t >= nE * Np) return;
-  const int e = t / Np, i = t - e * Np;
+  // two threads per node: the first nE Np threads take the velocity
+  // derivatives G (memory psi, stress terms), the next nE Np the stress
+  // derivatives D (memory phi, velocity terms); each half touches its own
+  // nine memory variables and its own fields
+  if (tid >= 2 * nE * Np) return;
+  const bool vel = tid < nE * Np;
+  const int u = vel ? tid : tid - nE * Np;
+  const int e = u / Np, i = u - e * Np;
   const int64_t pi = p0 + e;
   const int64_t k = sk[e];
   const real *qe = sq + e * 9 * Np;
   const double *g = smeta + e * DGW_META;
-  // the node's memory variables and profile: loads issued before the
-  // derivative loops so their latency is hidden
-  real mv[18];
-  const int64_t mb = pi * 18 * Np + i;
+  // an opaque zero added to the operator addresses keeps the compiler from
+  // hoisting every operator load out of the chunked loops (far beyond the
+  // register file)
+  int oz;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(oz));
+  constexpr int UJ = Np % 7 == 0 ? 7 : Np % 5 == 0 ? 5 : 4;   // divides Np
+  // reference derivatives of the role's fields: velocity (3) or stress (6)
+  const int c0 = vel ? 0 : 3;
+  real acc[6][3];
 #pragma unroll
-  for (int j = 0; j < 18; ++j) mv[j] = mem[mb + j * Np];
+  for (int c = 0; c < 6; ++c) acc[c][0] = acc[c][1] = acc[c][2] = (real)0;
+  {
+    const real *pr = A.DrT + i + oz, *ps = A.DsT + i + oz, *pt = A.DtT + i + oz;
+#pragma unroll 1
+    for (int j0 = 0; j0 < Np; j0 += UJ) {
+#pragma unroll
+      for (int w = 0; w < UJ; ++w) {
+        const real a0 = pr[w * Np], a1 = ps[w * Np], a2 = pt[w * Np];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          if (vel && c >= 3) continue;
+          const real v = qe[(c0 + c) * Np + j0 + w];
+          acc[c][0] += a0 * v;
+          acc[c][1] += a1 * v;
+          acc[c][2] += a2 * v;
+        }
+      }
+      pr += UJ * Np;
+      ps += UJ * Np;
+      pt += UJ * Np;
+    }
+  }
+  real X[9];
+#pragma unroll
+  for (int w = 0; w < 9; ++w) X[w] = (real)g[M_XINV + w];
+  // sigma_cb in Voigt order (xx yy zz yz xz xy) as stress index 0..5
+  constexpr int vo[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+  real Dg[3][3];   // G (velocity role) or D (stress role), [c][b]
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int s = vel ? c : vo[c][b];
+      Dg[c][b] = X[b] * acc[s][0] + X[3 + b] * acc[s][1] + X[6 + b] * acc[s][2];
+    }
+  // face part: the lifted traction change W (stress role) or velocity
+  // change U (velocity role) of each face, with the face's normal
+  {
+    const real *fle = sfl + e * NF * 6 + (vel ? 3 : 0);
+    const real *pl = A.LIFTT + i + oz;
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+      real W0 = 0, W1 = 0, W2 = 0;
+#pragma unroll
+      for (int m = 0; m < Nfp; ++m) {
+        const real l = pl[(f * Nfp + m) * Np];
+        const real *s3 = fle + (f * Nfp + m) * 6;
+        W0 += l * s3[0];
+        W1 += l * s3[1];
+        W2 += l * s3[2];
+      }
+      const real n[3] = {(real)g[M_NORMAL + 3 * f], (real)g[M_NORMAL + 3 * f + 1],
+                         (real)g[M_NORMAL + 3 * f + 2]};
+      const real Wv[3] = {W0, W1, W2};
+      if (vel) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) Dg[c][b] += n[b] * Wv[c];
+      } else {
+        // n is constant on the face, so the lift of n_b S_cb is
+        // n_b (W_c n_b + n_c W_b - n_c n_b (n.W))
+        const real nW = n[0] * W0 + n[1] * W1 + n[2] * W2;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+            Dg[c][b] += n[b] * (Wv[c] * n[b] + n[c] * Wv[b] - n[c] * n[b] * nW);
+      }
+    }
+  }
+  // the role's nine memory variables (phi for the stress role, psi for the
+  // velocity role) at the stage input, and the node's profile
+  const int64_t mb = pi * 18 * Np + (vel ? 9 * Np : 0) + i;
+  real mv[9];
+#pragma unroll
+  for (int w = 0; w < 9; ++w) mv[w] = mem[mb + w * Np];
   real db[3], ab[3];
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
     db[b] = (real)A.prof[(pi * 6 + b) * Np + i];
     ab[b] = (real)A.prof[(pi * 6 + 3 + b) * Np + i];
   }
-  real dr[9], ds[9], dtt[9];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) dr[c] = ds[c] = dtt[c] = (real)0;
-  for (int j = 0; j < Np; ++j) {
-    const real a0 = A.DrT[j * Np + i], a1 = A.DsT[j * Np + i], a2 = A.DtT[j * Np + i];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      const real v = qe[c * Np + j];
-      dr[c] += a0 * v;
-      ds[c] += a1 * v;
-      dtt[c] += a2 * v;
-    }
-  }
-  real X[9];
-#pragma unroll
-  for (int u = 0; u < 9; ++u) X[u] = (real)g[M_XINV + u];
-  // sigma_cb in Voigt order (xx yy zz yz xz xy) as field index
-  constexpr int vo[3][3] = {{3, 8, 7}, {8, 4, 6}, {7, 6, 5}};
-  real Dd[3][3], Gd[3][3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const int s = vo[c][b];
-      Dd[c][b] = X[b] * dr[s] + X[3 + b] * ds[s] + X[6 + b] * dtt[s];
-      Gd[c][b] = X[b] * dr[c] + X[3 + b] * ds[c] + X[6 + b] * dtt[c];
-    }
-  const real *fle = sfl + e * NF * 6;
-  for (int f = 0; f < 4; ++f) {
-    real W[3] = {0, 0, 0}, U[3] = {0, 0, 0};
-#pragma unroll
-    for (int m = 0; m < Nfp; ++m) {
-      const real l = A.LIFTT[(f * Nfp + m) * Np + i];
-      const real *s6 = fle + (f * Nfp + m) * 6;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        W[c] += l * s6[c];
-        U[c] += l * s6[3 + c];
-      }
-    }
-    const real n[3] = {(real)g[M_NORMAL + 3 * f], (real)g[M_NORMAL + 3 * f + 1],
-                       (real)g[M_NORMAL + 3 * f + 2]};
-    const real nW = n[0] * W[0] + n[1] * W[1] + n[2] * W[2];
-    // n is constant on the face, so the lift of n_b S_cb is
-    // n_b (W_c n_b + n_c W_b - n_c n_b (n.W)) with W the lifted dT
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        Dd[c][b] += n[b] * (W[c] * n[b] + n[c] * W[b] - n[c] * n[b] * nW);
-        Gd[c][b] += n[b] * U[c];
-      }
-  }
-  // layer terms of the stage input's memory variables
-  const real ri = (real)g[M_RHOINV], la = (real)g[M_LAM], mu = (real)g[M_MU];
-  real dl[9];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) dl[c] = ri * (mv[3 * c] + mv[3 * c + 1] + mv[3 * c + 2]);
-  const real tr = mv[9] + mv[13] + mv[17];   // psi_xx + psi_yy + psi_zz
-  dl[3] = la * tr + 2 * mu * mv[9];
-  dl[4] = la * tr + 2 * mu * mv[13];
-  dl[5] = la * tr + 2 * mu * mv[17];
-  dl[6] = mu * (mv[9 + 5] + mv[9 + 7]);      // psi_yz + psi_zy
-  dl[7] = mu * (mv[9 + 2] + mv[9 + 6]);      // psi_xz + psi_zx
-  dl[8] = mu * (mv[9 + 1] + mv[9 + 3]);      // psi_xy + psi_yx
   const real ra = (real)A.rk_a, rb = (real)A.rk_b, rdt = (real)A.dt;
+  // the layer's terms: (1/rho) sum_b phi_cb on v_c, or
+  // lambda tr(Psi) I + mu (Psi + Psi^T) on sigma
+  if (vel) {
+    const real la = (real)g[M_LAM], mu = (real)g[M_MU];
+    const real tr = mv[0] + mv[4] + mv[8];
+    const real dl[6] = {la * tr + 2 * mu * mv[0], la * tr + 2 * mu * mv[4],
+                        la * tr + 2 * mu * mv[8], mu * (mv[5] + mv[7]),
+                        mu * (mv[2] + mv[6]), mu * (mv[1] + mv[3])};
 #pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    const int64_t idx = (k * 9 + c) * Np + i;
-    const real add = rdt * dl[c];
-    res[idx] = res[idx] + add;
-    qout[idx] = qout[idx] + rb * add;
+    for (int c = 0; c < 6; ++c) {
+      const int64_t idx = (k * 9 + 3 + c) * Np + i;
+      const real add = rdt * dl[c];
+      res[idx] = res[idx] + add;
+      qout[idx] = qout[idx] + rb * add;
+    }
+  } else {
+    const real ri = (real)g[M_RHOINV];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t idx = (k * 9 + c) * Np + i;
+      const real add = rdt * (ri * (mv[3 * c] + mv[3 * c + 1] + mv[3 * c + 2]));
+      res[idx] = res[idx] + add;
+      qout[idx] = qout[idx] + rb * add;
+    }
   }
+  // memory update: m_t = -(d_b + alpha_b) m_cb - d_b (D or G)_cb
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const int jp = 3 * c + b, js = 9 + 3 * c + b;
-      const real rp = -(db[b] + ab[b]) * mv[jp] - db[b] * Dd[c][b];
-      const real rs = -(db[b] + ab[b]) * mv[js] - db[b] * Gd[c][b];
+      const int w = 3 * c + b;
+      const real rate = -(db[b] + ab[b]) * mv[w] - db[b] * Dg[c][b];
       // stage 1 (a = 0) never reads mres, so stale values cannot leak in
-      const real np_ = (A.rk_a == 0.0) ? rdt * rp : ra * mres[mb + jp * Np] + rdt * rp;
-      const real ns_ = (A.rk_a == 0.0) ? rdt * rs : ra * mres[mb + js * Np] + rdt * rs;
-      mres[mb + jp * Np] = np_;
-      mres[mb + js * Np] = ns_;
-      mem[mb + jp * Np] = mv[jp] + rb * np_;
-      mem[mb + js * Np] = mv[js] + rb * ns_;
+      const real r = (A.rk_a == 0.0) ? rdt * rate : ra * mres[mb + w * Np] + rdt * rate;
+      mres[mb + w * Np] = r;
+      mem[mb + w * Np] = mv[w] + rb * r;
     }
 }
 

@@ -144,3 +144,126 @@ def test_memory_rate_at_rest_is_minus_d_times_the_derivative():
         for b in range(3):
             assert torch.equal(r[:, 3 * c + b], -d[:, b] * D[:, c, b])
             assert torch.equal(r[:, 9 + 3 * c + b], -d[:, b] * G[:, c, b])
+
+
+# ---- absorption against the sponge ------------------------------------------
+
+H = 0.25            # cell size of the columns (3 x 3 cells across, periodic)
+CP, CS, RHO = 2.0, 1.2, 1.0
+
+
+def _column(nx, ny, N, free_end):
+    mesh = W.kuhn_box(nx, ny, 3, nx * H, ny * H, 3 * H, periodic=(False, True, True),
+                      free_faces=("x+",) if free_end else ())
+    K = mesh["etov"].shape[0]
+    P = O.Problem(mesh, N)
+    mat = tensors(*W.lame_from_velocities(np.full(K, CP), np.full(K, CS), np.full(K, RHO)))
+    return mesh, P, mat
+
+
+def _pulse(mesh, N, mat, direction, profile):
+    """P-wave travelling along `direction`: v = d f, sigma = -(lambda I +
+    2 mu d d^T) f / cp with f the given profile of the node coordinates."""
+    X = W.lattice_node_coords(mesh, N)
+    d = np.asarray(direction, dtype=np.float64)
+    lam, mu = float(mat[1][0]), float(mat[2][0])
+    S = -(lam * np.eye(3) + 2.0 * mu * np.outer(d, d)) / CP
+    f = profile(X)
+    q = np.zeros((X.shape[0], 9, X.shape[1]))
+    q[:, 0:3] = np.moveaxis(f[..., None] * d, -1, 1)
+    for a, (i, j) in enumerate([(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]):
+        q[:, 3 + a] = S[i, j] * f
+    return torch.as_tensor(q)
+
+
+def _reflections(direction, profile, ny, n_in, n_ref, T, t_meas, f0, sponges):
+    """Reflection amplitude of each absorber: the largest over t in
+    [t_meas, T] of sqrt(E_in(q - q_ref) / E_in(q0)), E_in the energy of the
+    interior cells x < n_in H.  The absorber (4 cells, width 1) sits between
+    the interior and a free surface; q_ref is the run on a column of n_ref
+    cells with no absorber, so long that nothing comes back before T.
+    Returns ({sigma_max: amplitude}, pml amplitude)."""
+    N, nl, dt = 2, 4, 0.02
+    nx = n_in + nl
+    mR, PR, matR = _column(n_ref, ny, N, False)
+    mA, PA, matA = _column(nx, ny, N, True)
+    # element of the reference column in the same cell and tetrahedron
+    e = np.arange(mA["etov"].shape[0])
+    c, p = e // 6, e % 6
+    i, j, k = c % nx, (c // nx) % ny, c // (nx * ny)
+    to_ref = torch.as_tensor(6 * (i + n_ref * (j + ny * k)) + p)
+    assert np.allclose(mR["vxyz"][mR["etov"][to_ref.numpy()]], mA["vxyz"][mA["etov"]])
+    inner = torch.as_tensor(W.element_centroids(mA)[:, 0] < n_in * H)
+
+    def e_in(dq):
+        z = dq.clone()
+        z[~inner] = 0
+        return O.energy(PA, z, *matA).item()
+
+    nsteps = int(round(T / dt))
+    meas = [s for s in range(nsteps) if (s + 1) * dt >= t_meas - 1e-9 and (s + 1) % 5 == 0]
+    q = _pulse(mR, N, matR, direction, profile)
+    ref = {}
+    for s in range(nsteps):
+        q = O.lserk_step(PR, q, s * dt, dt, *matR)
+        if s in meas:
+            ref[s] = q[to_ref]
+    q0 = _pulse(mA, N, matA, direction, profile)
+    E0 = e_in(q0)
+    hi = (nx * H, ny * H, 3 * H)
+    cen = W.element_centroids(mA)
+
+    def amplitude(step):
+        q, m, worst = q0, None, 0.0
+        for s in range(nsteps):
+            q, m = step(q, m, s)
+            if s in meas:
+                worst = max(worst, e_in(q - ref[s]))
+        return math.sqrt(worst / E0)
+
+    out = {}
+    for sm in sponges:
+        PA.sponge = torch.as_tensor(W.sponge_profile(cen, hi=hi, width=nl * H,
+                                                     sigma_max=sm, faces=("x+",)))
+        out[sm] = amplitude(lambda q, m, s: (O.lserk_step(PA, q, s * dt, dt, *matA), None))
+    PA.sponge = None
+    _, _, d, a = W.pml_layer(mA, N, hi=hi, width=nl * H, cp_max=CP, reflection=1e-4,
+                             f0=f0, faces=("x+",))
+    d, a = torch.as_tensor(d), torch.as_tensor(a)
+    zero_m = torch.zeros(q0.shape[0], 18, PA.Np, dtype=torch.float64)
+    pml = amplitude(lambda q, m, s: OP.lserk_step(PA, q, zero_m if m is None else m,
+                                                  s * dt, dt, *matA, d, a))
+    return out, pml
+
+
+def test_pml_reflects_less_than_the_sponge_at_normal_incidence():
+    # Ricker pulse of peak frequency 1 (wavelength 2) at x = 1.5; the layer
+    # is half a wavelength wide
+    f0 = 1.0
+
+    def ricker(X):
+        a2 = (math.pi * f0 * (X[..., 0] - 1.5) / CP) ** 2
+        return (1.0 - 2.0 * a2) * np.exp(-a2)
+
+    sp, pml = _reflections((1.0, 0.0, 0.0), ricker, ny=3, n_in=12, n_ref=34, T=3.2,
+                           t_meas=1.6, f0=f0, sponges=(16.0, 32.0, 64.0))
+    # measured: sponge 5.4e-3, 2.3e-3, >= 2.3e-3; layer 8.2e-4
+    best = min(sp.values())
+    assert best < 0.05 and pml < 0.5 * best, (sp, pml)
+
+
+def test_pml_reflects_less_than_the_sponge_at_oblique_incidence():
+    # wave packet at 45 degrees: wavevector (k, k, 0)/sqrt(2) with k sin 45
+    # one period across the 1.5-wide periodic column, Gaussian envelope in x
+    ny = 6
+    k = (2.0 * math.pi / (ny * H)) / math.sin(math.pi / 4)
+    d = np.array([1.0, 1.0, 0.0]) / math.sqrt(2.0)
+    w = 1.2 * CP / (math.pi * 2.0)
+
+    def packet(X):
+        return np.exp(-((X[..., 0] - 1.0) / w) ** 2) * np.cos(k * (X @ d - d[0]))
+
+    sp, pml = _reflections(d, packet, ny=ny, n_in=8, n_ref=22, T=2.5, t_meas=1.0,
+                           f0=2.0, sponges=(16.0, 32.0))
+    # measured: sponge 9.9e-2, 1.2e-1; layer 3.0e-3
+    assert pml < 0.1 * min(sp.values()), (sp, pml)
