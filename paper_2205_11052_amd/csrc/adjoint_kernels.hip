@@ -417,18 +417,16 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
   }
   __syncthreads();
 
-  // ---- nodes: two independent halves, each one thread per (element,
-  //      node): the transposed volume term and the update of the adjoint
-  //      state, and the forward volume term for the gradient.  The halves
-  //      start on a wavefront boundary so each wave runs one branch.
+  // ---- nodes: one thread per (element, node): the transposed volume term,
+  //      the update of the adjoint state, and the volume part of the
+  //      gradient.  The gradient's volume terms are sums over nodes of w
+  //      times physical derivatives of q; by w^T D q = (D^T w)^T q they are
+  //      taken from the transposed derivatives already formed here, dotted
+  //      with q at the node, so no forward derivative pass is needed.
   constexpr int UJ = Np % 7 == 0 ? 7 : Np % 5 == 0 ? 5 : 4;  // divides Np
   const int nodes = nE * Np;
-  const int half = (nodes + 63) / 64 * 64;
-  for (int t = tid; t < 2 * half; t += kT) {
-    const bool transposed = t < half;
-    const int tt = transposed ? t : t - half;
-    if (tt >= nodes) continue;
-    const int e = tt / Np, i = tt - e * Np;
+  for (int t = tid; t < nodes; t += kT) {
+    const int e = t / Np, i = t - e * Np;
     const int64_t k = k0 + e;
     const double *g = smeta + e * DGW_META;
     real X[9];
@@ -436,13 +434,15 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
     for (int u = 0; u < 9; ++u) X[u] = (real)g[M_XINV + u];
     const real ri = (real)g[M_RHOINV], la = (real)g[M_LAM], mu = (real)g[M_MU];
     const real *we = sw + e * 9 * Np;
-    // d_r, d_s, d_t of the nine fields of v at node i: operator column i of
-    // Op (given transposed, [j][i]), walked in chunks of immediate offsets
-    auto derivs = [&](const real *OpR, const real *OpS, const real *OpT, const real *v,
-                      real (&dr)[9], real (&ds)[9], real (&dt)[9]) {
+    const real *qe = sq + e * 9 * Np;
+    // D_r^T w, D_s^T w, D_t^T w of the nine fields at node i: column i of
+    // D_a^T is row i of D_a, stored [j][i] = D(j, i), walked in chunks of
+    // immediate offsets
+    real ar[9], as[9], at[9];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) dr[c] = ds[c] = dt[c] = 0;
-      const real *pr = OpR + i, *ps = OpS + i, *pt = OpT + i;
+    for (int c = 0; c < 9; ++c) ar[c] = as[c] = at[c] = 0;
+    {
+      const real *pr = A.Dr + i, *ps = A.Ds + i, *pt = A.Dt + i;
 #pragma unroll 1
       for (int j0 = 0; j0 < Np; j0 += UJ) {
 #pragma unroll
@@ -450,82 +450,84 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
           const real a0 = pr[u * Np], a1 = ps[u * Np], a2 = pt[u * Np];
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
-            const real x = v[c * Np + j0 + u];
-            dr[c] += a0 * x;
-            ds[c] += a1 * x;
-            dt[c] += a2 * x;
+            const real x = we[c * Np + j0 + u];
+            ar[c] += a0 * x;
+            as[c] += a1 * x;
+            at[c] += a2 * x;
           }
         }
         pr += UJ * Np;
         ps += UJ * Np;
         pt += UJ * Np;
       }
+    }
+    // sum_a X^-1[a][b] (D_a^T w_c) at node i
+    auto DTw = [&](int c, int bb) -> real {
+      return X[bb] * ar[c] + X[3 + bb] * as[c] + X[6 + bb] * at[c];
     };
-    if (transposed) {
-      // D_r^T w: column i of D_r^T is row i of D_r stored [j][i] as Dr
-      real ar[9], as[9], at[9];
-      derivs(A.Dr, A.Ds, A.Dt, we, ar, as, at);
-      auto DTw = [&](int c, int bb) -> real {
-        return X[bb] * ar[c] + X[3 + bb] * as[c] + X[6 + bb] * at[c];
-      };
-      real adj[9];
-      // velocity: sum_b d_b^T T_ab, T_aa = la tr(w_s) + 2 mu w_aa, T_ab = mu w_ab
-      adj[0] = la * (DTw(3, 0) + DTw(4, 0) + DTw(5, 0)) + 2 * mu * DTw(3, 0) +
-               mu * (DTw(8, 1) + DTw(7, 2));
-      adj[1] = la * (DTw(3, 1) + DTw(4, 1) + DTw(5, 1)) + 2 * mu * DTw(4, 1) +
-               mu * (DTw(8, 0) + DTw(6, 2));
-      adj[2] = la * (DTw(3, 2) + DTw(4, 2) + DTw(5, 2)) + 2 * mu * DTw(5, 2) +
-               mu * (DTw(7, 0) + DTw(6, 1));
-      // stress: (1/rho) d^T of the velocity adjoints
-      adj[3] = ri * DTw(0, 0);
-      adj[4] = ri * DTw(1, 1);
-      adj[5] = ri * DTw(2, 2);
-      adj[6] = ri * (DTw(1, 2) + DTw(2, 1));
-      adj[7] = ri * (DTw(0, 2) + DTw(2, 0));
-      adj[8] = ri * (DTw(0, 1) + DTw(1, 0));
-      // the sponge's -sigma q is its own transpose
-      if (A.sponge) {
-        const real sg = (real)A.sponge[k];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) adj[c] -= sg * we[c * Np + i];
-      }
-      const real *fa = sfa + e * 9 * NF;
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const int mm = A.facepos[f * Np + i];
-        if (mm >= 0) {
-#pragma unroll
-          for (int c = 0; c < 9; ++c) adj[c] += fa[c * NF + f * Nfp + mm];
-        }
-      }
-      const real rdt = (real)A.dt, ra = (real)A.rk_a;
-#pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        const int64_t idx = (k * 9 + c) * Np + i;
-        lq[idx] += rdt * adj[c];
-        lr[idx] = ra * we[c * Np + i];
-      }
-    } else {
-      // forward D q for the volume gradient terms at this node
-      real fr[9], fs[9], ft[9];
-      derivs(A.DrT, A.DsT, A.DtT, sq + e * 9 * Np, fr, fs, ft);
-      auto Dq = [&](int c, int bb) -> real {
-        return X[bb] * fr[c] + X[3 + bb] * fs[c] + X[6 + bb] * ft[c];
-      };
-      const real divv = Dq(0, 0) + Dq(1, 1) + Dq(2, 2);
-      const real ds0 = Dq(3, 0) + Dq(8, 1) + Dq(7, 2);
-      const real ds1 = Dq(8, 0) + Dq(4, 1) + Dq(6, 2);
-      const real ds2 = Dq(7, 0) + Dq(6, 1) + Dq(5, 2);
-      const double w0 = we[0 * Np + i], w1 = we[1 * Np + i], w2 = we[2 * Np + i];
-      const double w3 = we[3 * Np + i], w4 = we[4 * Np + i], w5 = we[5 * Np + i];
-      const double w6 = we[6 * Np + i], w7 = we[7 * Np + i], w8 = we[8 * Np + i];
+    real adj[9];
+    // velocity: sum_b d_b^T T_ab, T_aa = la tr(w_s) + 2 mu w_aa, T_ab = mu w_ab
+    adj[0] = la * (DTw(3, 0) + DTw(4, 0) + DTw(5, 0)) + 2 * mu * DTw(3, 0) +
+             mu * (DTw(8, 1) + DTw(7, 2));
+    adj[1] = la * (DTw(3, 1) + DTw(4, 1) + DTw(5, 1)) + 2 * mu * DTw(4, 1) +
+             mu * (DTw(8, 0) + DTw(6, 2));
+    adj[2] = la * (DTw(3, 2) + DTw(4, 2) + DTw(5, 2)) + 2 * mu * DTw(5, 2) +
+             mu * (DTw(7, 0) + DTw(6, 1));
+    // stress: (1/rho) d^T of the velocity adjoints
+    adj[3] = ri * DTw(0, 0);
+    adj[4] = ri * DTw(1, 1);
+    adj[5] = ri * DTw(2, 2);
+    adj[6] = ri * (DTw(1, 2) + DTw(2, 1));
+    adj[7] = ri * (DTw(0, 2) + DTw(2, 0));
+    adj[8] = ri * (DTw(0, 1) + DTw(1, 0));
+    // volume gradient at node i (FP64 sums), from
+    //   rho:    -rho^-2 w_v . div(sigma)
+    //   lambda: tr(w_s) div(v)
+    //   mu:     2 sum_b w_bb d_b v_b + w_yz (d_z v_y + d_y v_z) + ...
+    // with each w . d_b q_c moved onto (D^T w) q_c
+    {
+      const double q0 = qe[0 * Np + i], q1 = qe[1 * Np + i], q2 = qe[2 * Np + i];
+      const double q3 = qe[3 * Np + i], q4 = qe[4 * Np + i], q5 = qe[5 * Np + i];
+      const double q6 = qe[6 * Np + i], q7 = qe[7 * Np + i], q8 = qe[8 * Np + i];
       const double rinv = g[M_RHOINV];
-      sgv[(e * 3 + 0) * Np + i] = -rinv * rinv * (w0 * ds0 + w1 * ds1 + w2 * ds2);
-      sgv[(e * 3 + 1) * Np + i] = (w3 + w4 + w5) * (double)divv;
-      sgv[(e * 3 + 2) * Np + i] =
-          2.0 * (w3 * Dq(0, 0) + w4 * Dq(1, 1) + w5 * Dq(2, 2)) +
-          w6 * (double)(Dq(1, 2) + Dq(2, 1)) + w7 * (double)(Dq(0, 2) + Dq(2, 0)) +
-          w8 * (double)(Dq(0, 1) + Dq(1, 0));
+      const double sr = (double)DTw(0, 0) * q3 + (double)DTw(0, 1) * q8 +
+                        (double)DTw(0, 2) * q7 + (double)DTw(1, 0) * q8 +
+                        (double)DTw(1, 1) * q4 + (double)DTw(1, 2) * q6 +
+                        (double)DTw(2, 0) * q7 + (double)DTw(2, 1) * q6 +
+                        (double)DTw(2, 2) * q5;
+      const double sl = (double)(DTw(3, 0) + DTw(4, 0) + DTw(5, 0)) * q0 +
+                        (double)(DTw(3, 1) + DTw(4, 1) + DTw(5, 1)) * q1 +
+                        (double)(DTw(3, 2) + DTw(4, 2) + DTw(5, 2)) * q2;
+      const double sm = 2.0 * ((double)DTw(3, 0) * q0 + (double)DTw(4, 1) * q1 +
+                               (double)DTw(5, 2) * q2) +
+                        (double)DTw(6, 2) * q1 + (double)DTw(6, 1) * q2 +
+                        (double)DTw(7, 2) * q0 + (double)DTw(7, 0) * q2 +
+                        (double)DTw(8, 1) * q0 + (double)DTw(8, 0) * q1;
+      sgv[(e * 3 + 0) * Np + i] = -rinv * rinv * sr;
+      sgv[(e * 3 + 1) * Np + i] = sl;
+      sgv[(e * 3 + 2) * Np + i] = sm;
+    }
+    // the sponge's -sigma q is its own transpose
+    if (A.sponge) {
+      const real sgm = (real)A.sponge[k];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) adj[c] -= sgm * we[c * Np + i];
+    }
+    const real *fa = sfa + e * 9 * NF;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int mm = A.facepos[f * Np + i];
+      if (mm >= 0) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) adj[c] += fa[c * NF + f * Nfp + mm];
+      }
+    }
+    const real rdt = (real)A.dt, ra = (real)A.rk_a;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const int64_t idx = (k * 9 + c) * Np + i;
+      lq[idx] += rdt * adj[c];
+      lr[idx] = ra * we[c * Np + i];
     }
   }
   __syncthreads();
