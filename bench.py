@@ -782,6 +782,19 @@ def main():
             secb, _ = timed_steps(torch, sb, stream, bsteps, 2)
             kb, _ = kernel_avg_ms(sb, 2)
             shapeb = sb.shape
+            # the whole uneven batch from rest to its last step: shots drop
+            # out as they reach their lengths, and the launches then cover
+            # the active shots only
+            progress("fp32 batch: full-length run")
+            sb.zero_fields()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            sb.step(int(lens.max()))
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sec_full = e0.elapsed_time(e1) / 1e3
         del sb
         forms["fp32_batched_32_shots"] = {
             "value": round(nb * dof * 5 * bsteps / secb / 1e9, 3),
@@ -794,7 +807,17 @@ def main():
                               / HBM_PEAK_GBS, 4),
             "launch_shape": list(shapeb),
             "note": "32 shots, one launch per stage over all shots, graph "
-                    "replay; lengths 500-2000 steps, all active in the window"}
+                    "replay; lengths 500-2000 steps, all active in the window",
+            "full_length": {
+                "shot_steps": int(lens.sum()),
+                "steps": int(lens.max()),
+                "s_total": round(sec_full, 3),
+                "ms_per_shot_step": round(sec_full / float(lens.sum()) * 1e3, 4),
+                "single_shot_ms_per_step": round(sec32 / args.steps * 1e3, 4),
+                "per_shot_step_vs_single": round((sec32 / args.steps)
+                                                 / (sec_full / float(lens.sum())), 3),
+                "note": "every shot from rest to its own length in one run; "
+                        "finished shots leave the launches"}}
         progress("fp32 and batched forms done")
         forms["order6"] = order6_form(torch, stream, w, max(20, args.steps // 5), 2)
         progress("order-6 form done")

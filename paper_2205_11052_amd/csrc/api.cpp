@@ -368,14 +368,17 @@ int dgw_ctx::enqueue_step(int from, bool timed) {
     if (timed && ev_pool_used + 2 <= (int)ev_pool.size()) {
       (void)hipEventRecord(ev_pool[ev_pool_used], stream);
     }
+    const int ns = slots > 0 ? slots : nshots;
     if (precision == 64) {
       StageArgs<double> a;
       stage_args(this, a, d_q[from], d_q[1 - from], d_res, d_step, i);
-      e = launch_stage(kernel, R.N, 64, block, wpc, ncu, nshots, &a, stream);
+      a.shot_map = mapped ? d_shot_map : nullptr;
+      e = launch_stage(kernel, R.N, 64, block, wpc, ncu, ns, &a, stream);
     } else {
       StageArgs<float> a;
       stage_args(this, a, d_q[from], d_q[1 - from], d_res, d_step, i);
-      e = launch_stage(kernel, R.N, 32, block, wpc, ncu, nshots, &a, stream);
+      a.shot_map = mapped ? d_shot_map : nullptr;
+      e = launch_stage(kernel, R.N, 32, block, wpc, ncu, ns, &a, stream);
     }
     if (e != hipSuccess) return hipfail(e, "stage kernel launch");
     if (timed && ev_pool_used + 2 <= (int)ev_pool.size()) {
@@ -429,6 +432,7 @@ int dgw_ctx::enqueue_pml(const void *in, void *out, int stage, bool timed) {
     a.nP = pml_n;
     a.shot_stride = mesh.K * 9 * R.Np;
     a.mem_stride = pml_n * 18 * R.Np;
+    a.shot_map = mapped ? d_shot_map : nullptr;
     a.shot_step = d_step;
     a.shot_len = d_len;
     a.ftau = (real)flux_tau;
@@ -436,15 +440,16 @@ int dgw_ctx::enqueue_pml(const void *in, void *out, int stage, bool timed) {
     a.rk_b = dgw::rk_b()[stage];
     a.dt = dt;
   };
+  const int ns = slots > 0 ? slots : nshots;
   hipError_t e;
   if (precision == 64) {
     PmlArgs<double> a;
     fill(a);
-    e = launch_pml(R.N, 64, nshots, &a, stream);
+    e = launch_pml(R.N, 64, ns, &a, stream);
   } else {
     PmlArgs<float> a;
     fill(a);
-    e = launch_pml(R.N, 32, nshots, &a, stream);
+    e = launch_pml(R.N, 32, ns, &a, stream);
   }
   if (e != hipSuccess) return hipfail(e, "layer kernel launch");
   if (ev) {
@@ -493,6 +498,31 @@ int dgw_ctx::build_graph() {
   if (e != hipSuccess) return hipfail(e, "hipGraphInstantiate");
   graph_ok = true;
   graph_from = cur;
+  graph_slots = slots;
+  return DGW_OK;
+}
+
+// Launch only the listed shots (strictly increasing ids) from here on; the
+// full list restores the uncompacted launches.  The map is uploaded on the
+// context's stream and waited for, so the host list may change afterwards.
+int dgw_ctx::set_active(const std::vector<int32_t> &active) {
+  const bool all = (int)active.size() == nshots;
+  const int want = all ? nshots : (int)active.size();
+  if (want == slots && all == !mapped && (all || active == h_shot_map)) return DGW_OK;
+  invalidate_graph();
+  slots = want;
+  mapped = !all;
+  h_shot_map = active;
+  if (all) return DGW_OK;
+  if (!d_shot_map) {
+    d_shot_map = (int32_t *)dalloc(sizeof(int32_t) * nshots);
+    if (!d_shot_map) return fail(DGW_ENOMEM, "device allocation failed (shot map)");
+  }
+  hipError_t e = hipMemcpyAsync(d_shot_map, active.data(), sizeof(int32_t) * active.size(),
+                                hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hipfail(e, "hipMemcpyAsync (shot map)");
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hipfail(e, "hipStreamSynchronize");
   return DGW_OK;
 }
 
@@ -802,19 +832,33 @@ int dgw_step(dgw_ctx *c, int64_t nsteps) {
     }
     c->pml_ev_used = 0;
   }
+  // segments of steps with a fixed set of active shots: a shot advancing
+  // adv[s] steps is active in the segments before step adv[s]; each segment
+  // launches the blocks of its active shots only
+  std::vector<int64_t> ends;
+  for (int s = 0; s < c->nshots; ++s)
+    if (adv[s] > 0) ends.push_back(adv[s]);
+  std::sort(ends.begin(), ends.end());
+  ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
   int64_t done = 0;
-  if (!timed && longest >= kGraphSteps) {
-    if (!c->graph_ok || c->graph_from != c->cur)
-      if ((rc = c->build_graph())) return rc;
-    for (; done + kGraphSteps <= longest; done += kGraphSteps) {
-      hipError_t e = hipGraphLaunch(c->graph_exec, c->stream);
-      if (e != hipSuccess) return c->hipfail(e, "hipGraphLaunch");
-      // kGraphSteps is even: the buffer roles are unchanged
+  for (int64_t end : ends) {
+    std::vector<int32_t> active;
+    for (int s = 0; s < c->nshots; ++s)
+      if (adv[s] >= end) active.push_back(s);
+    if ((rc = c->set_active(active))) return rc;
+    if (!timed && end - done >= kGraphSteps) {
+      if (!c->graph_ok || c->graph_from != c->cur || c->graph_slots != c->slots)
+        if ((rc = c->build_graph())) return rc;
+      for (; done + kGraphSteps <= end; done += kGraphSteps) {
+        hipError_t e = hipGraphLaunch(c->graph_exec, c->stream);
+        if (e != hipSuccess) return c->hipfail(e, "hipGraphLaunch");
+        // kGraphSteps is even: the buffer roles are unchanged
+      }
     }
-  }
-  for (; done < longest; ++done) {
-    if ((rc = c->enqueue_step(c->cur, timed))) return rc;
-    c->cur = 1 - c->cur;
+    for (; done < end; ++done) {
+      if ((rc = c->enqueue_step(c->cur, timed))) return rc;
+      c->cur = 1 - c->cur;
+    }
   }
   for (int s = 0; s < c->nshots; ++s) {
     c->h_step[s] += adv[s];

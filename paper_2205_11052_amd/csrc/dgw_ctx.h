@@ -83,6 +83,15 @@ struct dgw_ctx {
   hipGraphExec_t graph_exec = nullptr;
   bool graph_ok = false;
   int graph_from = 0;
+  // active-shot compaction of dgw_step: while some shots of the batch have
+  // finished, the stage and layer launches cover only the active ones,
+  // listed in d_shot_map (slots = their count); slots = nshots and no map
+  // when every shot is active
+  int32_t *d_shot_map = nullptr;
+  std::vector<int32_t> h_shot_map;
+  int slots = 0;
+  bool mapped = false;
+  int graph_slots = -1;                // launch slots the graph was captured with
 
   // Bumped by every call that changes what a run computes (setters,
   // dgw_set_fields, dgw_step); the checkpointed forward records it and the
@@ -136,6 +145,7 @@ struct dgw_ctx {
   int clear_pml(int shot);                 // zero a shot's memory variables (-1: all)
   int build_graph();
   int gather_shots_to_cur(const std::vector<int64_t> &adv);
+  int set_active(const std::vector<int32_t> &active);
   void free_adjoint();
 };
 
@@ -160,6 +170,7 @@ inline void stage_args(const dgw_ctx *c, dgw::StageArgs<real> &a, const void *in
   a.fmask = c->d_fmask;
   a.K = c->mesh.K;
   a.shot_stride = c->mesh.K * 9 * c->R.Np;
+  a.shot_map = nullptr;
   a.shot_step = steps;
   a.shot_len = c->d_len;
   a.src_elem = c->d_src_elem;

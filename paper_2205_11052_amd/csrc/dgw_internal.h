@@ -101,6 +101,10 @@ struct StageArgs {
   const int32_t *fmask;         // [4 Nfp]
   int64_t K;
   int64_t shot_stride;          // K * 9 * Np
+  // shot of each launched slot [slots], or null: slot s is shot s.  The
+  // launch covers `nshots` slots (the launchers' argument), so a batch whose
+  // finished shots are left out launches only the active shots' blocks.
+  const int32_t *shot_map;
   const int64_t *shot_step;     // [S]
   const int64_t *shot_len;      // [S]
   const int32_t *src_elem;      // [S] (-1: none)
@@ -133,6 +137,7 @@ struct PmlArgs {
   int64_t nP;
   int64_t shot_stride;          // K * 9 * Np
   int64_t mem_stride;           // nP * 18 * Np
+  const int32_t *shot_map;      // as in StageArgs
   const int64_t *shot_step;
   const int64_t *shot_len;
   real ftau;

@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(kPmlThreads) pml_kernel(PmlArgs<real> A) {
   __shared__ real sfl[PB * NF * 6];
   __shared__ double smeta[PB * DGW_META];
   __shared__ int64_t sk[PB];
-  const int shot = blockIdx.y;
+  const int shot = A.shot_map ? A.shot_map[blockIdx.y] : (int)blockIdx.y;
   if (A.shot_step[shot] >= A.shot_len[shot]) return;   // uniform per work-group
   const int64_t p0 = (int64_t)blockIdx.x * PB;
   if (p0 >= A.nP) return;

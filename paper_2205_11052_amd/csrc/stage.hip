@@ -451,8 +451,9 @@ template <int N, typename real, int BE>
 __device__ __forceinline__ void face_tables(const StageArgs<real> &A, int64_t item,
                                             int64_t nblk, FaceTab<N, BE> &T) {
   constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Nfp;
-  const int shot = (int)(item / nblk);
-  const int64_t k0 = (item - (int64_t)shot * nblk) * BE;
+  const int slot = (int)(item / nblk);
+  const int shot = A.shot_map ? A.shot_map[slot] : slot;
+  const int64_t k0 = (item - (int64_t)slot * nblk) * BE;
   const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
 #pragma unroll
   for (int u = 0; u < FaceTab<N, BE>::FI; ++u) {
@@ -492,8 +493,9 @@ __device__ __forceinline__ void block_loads(const StageArgs<real> &A, int64_t it
   constexpr int Np = Sz<N>::Np;
   using BL = BlockLoad<N, real, BE>;
   using SP = typename BL::SP;
-  const int shot = (int)(item / nblk);
-  const int64_t k0 = (item - (int64_t)shot * nblk) * BE;
+  const int slot = (int)(item / nblk);
+  const int shot = A.shot_map ? A.shot_map[slot] : slot;
+  const int64_t k0 = (item - (int64_t)slot * nblk) * BE;
   const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
   const int tid = threadIdx.x;
   // every load is unconditional, with out-of-range lanes clamped to an
@@ -537,10 +539,11 @@ __device__ __forceinline__ void stage_item(const StageArgs<real> &A, int64_t ite
   __shared__ __attribute__((aligned(16))) real sfl[BE * NF * (V == 1 || V == 3 ? 9 : 6)];
   __shared__ double smeta[BE * DGW_META];
   __shared__ double ssig[BE];
-  const int shot = (int)(item / nblk);
+  const int slot = (int)(item / nblk);
+  const int shot = A.shot_map ? A.shot_map[slot] : slot;
   const int64_t step = A.shot_step[shot];
   if (step >= A.shot_len[shot]) return;            // uniform per work-group
-  const int64_t k0 = (item - (int64_t)shot * nblk) * BE;
+  const int64_t k0 = (item - (int64_t)slot * nblk) * BE;
   // never taken (items cover the mesh exactly), but it bounds nE to
   // [1, BE] for the compiler, which keeps the register count low
   if (k0 >= A.K) return;

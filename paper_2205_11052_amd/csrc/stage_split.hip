@@ -94,10 +94,11 @@ stage_split_kernel(StageArgs<real> A, int64_t nblk, int64_t total) {
   __shared__ real sf0[3 * kBE * NpG];   // face-0 lift of each velocity component
 
   const int64_t item = xcd_item(blockIdx.x, total);
-  const int shot = (int)(item / nblk);
+  const int slot = (int)(item / nblk);
+  const int shot = A.shot_map ? A.shot_map[slot] : slot;
   const int64_t step = A.shot_step[shot];
   if (step >= A.shot_len[shot]) return;            // uniform per work-group
-  const int64_t k0 = (item - (int64_t)shot * nblk) * kBE;
+  const int64_t k0 = (item - (int64_t)slot * nblk) * kBE;
   if (k0 >= A.K) return;                           // never taken; bounds nE
   const int nE = (int)((A.K - k0) < kBE ? (A.K - k0) : kBE);
   const real *__restrict__ qin = A.q_in + shot * A.shot_stride;
