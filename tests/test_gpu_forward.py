@@ -383,6 +383,44 @@ def test_batched_shots_match_single_shot_runs(precision, kernel):
     assert b.shot_steps(2) == 5 and b.shot_steps(0) == 7
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_compacted_batch_with_graph_replays(kernel):
+    """Shots of lengths 5, 27 and 40 in one 40-step call: after step 5 the
+    launches cover two shots, after step 27 one (each segment long enough
+    for captured-graph replays of its own active set); every shot equals its
+    single-shot run bitwise."""
+    if not supported(kernel, 3, 64):
+        pytest.skip("kernel not built for this order")
+    mesh = W.kuhn_cube(3, 1.0)
+    K = mesh["etov"].shape[0]
+    rho, lam, mu = _random_medium(K, 21)
+    N = 3
+    P = oracle_problem(mesh, N)
+    dt = P.suggest_dt(rho, lam, mu, 0.5)
+    srcs = np.array([[0.2, 0.3, 0.4], [0.7, 0.6, 0.5], [0.5, 0.5, 0.9]])
+    lens = [5, 27, 40]
+    rec = np.array([[0.4, 0.4, 1.0], [0.6, 0.2, 1.0]])
+    say("case compacted batch kernel=%d" % kernel)
+    b = gpu_solver(mesh, N, rho, lam, mu, dt, 64, nshots=3, kernel=kernel)
+    q0 = [random_fields(K, P.Np, 70 + i) for i in range(3)]
+    for i in range(3):
+        b.set_source(i, srcs[i], 6.0, 0.1, 1.0, nsteps=lens[i])
+        b.set_receivers(i, rec, 40)
+        b.set_fields(i, q0[i])
+    b.step(40)
+    for i in range(3):
+        assert b.shot_steps(i) == lens[i]
+        one = gpu_solver(mesh, N, rho, lam, mu, dt, 64, kernel=kernel)
+        one.set_source(0, srcs[i], 6.0, 0.1, 1.0, nsteps=lens[i])
+        one.set_receivers(0, rec, 40)
+        one.set_fields(0, q0[i])
+        one.step(40)
+        assert np.array_equal(b.get_fields(i), one.get_fields(0))
+        assert np.array_equal(b.read_traces(i), one.read_traces(0))
+        one.close()
+    b.close()
+
+
 def test_tiny_mesh_smaller_than_a_block_and_zero_steps():
     mesh = W.kuhn_cube(1, 1.0)
     K = mesh["etov"].shape[0]
