@@ -70,7 +70,8 @@ typedef enum dgw_status {
   DGW_EHIP = -4,       /* a HIP runtime call failed (or no GPU present)    */
   DGW_ESTATE = -5,     /* call made in the wrong order                     */
   DGW_ERANGE = -6,     /* index or capacity out of range, point outside    */
-  DGW_ENONFINITE = -7  /* non-finite value detected in the fields          */
+  DGW_ENONFINITE = -7, /* non-finite value detected in the fields          */
+  DGW_EGROWTH = -8     /* a shot's energy grew past the watchdog's bound   */
 } dgw_status;
 
 /* Create a context for polynomial order 1..6, precision 64 (FP64 fields and
@@ -174,6 +175,20 @@ int dgw_energy_noalloc(dgw_ctx *ctx, int shot, double *E);
 
 /* DGW_ENONFINITE if any field value of any shot is NaN or infinite. */
 int dgw_check_finite(dgw_ctx *ctx);
+
+/* Step watchdog: with every > 0, dgw_step checks the fields after every
+ * `every` steps it runs (counted across calls): a NaN or infinite value in
+ * any shot stops the call with DGW_ENONFINITE, and with max_growth > 0 a
+ * shot whose discrete energy (dgw_energy) exceeds max_growth times its
+ * energy at the previous check stops it with DGW_EGROWTH; the message names
+ * the shot and its step.  The steps before the check have been taken (the
+ * fields stay readable).  A shot's energy baseline restarts when its fields
+ * are set; a baseline of zero (a shot at rest) is never exceeded.  The
+ * steps themselves are unchanged (results are identical with the watchdog
+ * on or off); each check synchronises the stream and costs one reduction
+ * per shot.  every = 0 turns it off.  DGW_EINVAL for every < 0, or
+ * max_growth negative, not finite, or in (0, 1). */
+int dgw_set_watchdog(dgw_ctx *ctx, int64_t every, double max_growth);
 
 /* Reference element of order N (host only, no context needed):
  * rst [Np][3] node coordinates; Dr, Ds, Dt [Np][Np] (d l_n / dr at node i in

@@ -9,7 +9,7 @@ _LIB = None
 DGW_OK = 0
 STATUS = {0: "DGW_OK", -1: "DGW_EINVAL", -2: "DGW_ENOMEM", -3: "DGW_EMESH",
           -4: "DGW_EHIP", -5: "DGW_ESTATE", -6: "DGW_ERANGE",
-          -7: "DGW_ENONFINITE"}
+          -7: "DGW_ENONFINITE", -8: "DGW_EGROWTH"}
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -41,6 +41,7 @@ SIGNATURES = {
     "dgw_energy": (C.c_int, [_P, C.c_int, _D]),
     "dgw_energy_noalloc": (C.c_int, [_P, C.c_int, _D]),
     "dgw_check_finite": (C.c_int, [_P]),
+    "dgw_set_watchdog": (C.c_int, [_P, _I64, C.c_double]),
     "dgw_ref_nodes": (C.c_int, [C.c_int, _D]),
     "dgw_ref_operators": (C.c_int, [C.c_int, _D, _D, _D, _D, _D]),
     "dgw_order_elements": (C.c_int, [_I64, _D, _I64, C.POINTER(C.c_int32),

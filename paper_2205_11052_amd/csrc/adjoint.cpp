@@ -134,6 +134,7 @@ extern "C" {
 int dgw_forward_checkpointed(dgw_ctx *c, int64_t nsteps, int64_t every,
                              const double *d_obs, double *misfit) {
   if (!c) return DGW_EINVAL;
+  RoctxRange range("dgw_forward_checkpointed");
   if (!c->have_mesh || !c->have_mat || !c->have_dt)
     return c->fail(DGW_ESTATE, "mesh, material and dt must be set first");
   if (nsteps < 1 || every < 1) return c->fail(DGW_EINVAL, "nsteps and ckpt_every must be >= 1");
@@ -225,6 +226,7 @@ int dgw_forward_checkpointed(dgw_ctx *c, int64_t nsteps, int64_t every,
 
 int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
   if (!c) return DGW_EINVAL;
+  RoctxRange range("dgw_adjoint");
   if (!c->adj || !c->adj->ready)
     return c->fail(DGW_ESTATE, "call dgw_forward_checkpointed first");
   if (c->adj->gen != c->gen)

@@ -772,6 +772,7 @@ int dgw_set_fields(dgw_ctx *c, int shot, const double *q) {
   }
   if (rc) return rc;
   if ((rc = c->clear_pml(shot))) return rc;
+  if (shot < (int)c->wd_energy.size()) c->wd_energy[shot] = 0.0;
   c->loc[shot] = c->cur;
   c->h_step[shot] = 0;
   if ((rc = c->upload(c->d_step + shot, &c->h_step[shot], sizeof(int64_t)))) return rc;
@@ -794,7 +795,7 @@ int dgw_get_fields(dgw_ctx *c, int shot, double *q) {
   return DGW_OK;
 }
 
-int dgw_step(dgw_ctx *c, int64_t nsteps) {
+static int step_core(dgw_ctx *c, int64_t nsteps) {
   if (!c) return DGW_EINVAL;
   if (!c->have_mesh || !c->have_mat || !c->have_dt)
     return c->fail(DGW_ESTATE, "mesh, material and dt must be set before stepping");
@@ -884,6 +885,80 @@ int dgw_step(dgw_ctx *c, int64_t nsteps) {
     c->pml_timed = c->pml_ev_used / 2;
     c->pml_ms = c->pml_timed ? ptot / c->pml_timed : 0.0;
   }
+  return DGW_OK;
+}
+
+// The watchdog's check after a chunk of steps: finiteness of every shot's
+// fields, then (with a growth bound) each shot's energy against its last.
+int dgw_ctx::watchdog_check() {
+  if (!d_flag) {
+    d_flag = (int *)dalloc(sizeof(int));
+    if (!d_flag) return fail(DGW_ENOMEM, "device allocation failed");
+  }
+  const int64_t n = mesh.K * 9 * R.Np;
+  for (int s = 0; s < nshots; ++s) {
+    int zero = 0, flag = 0, rc;
+    if ((rc = upload(d_flag, &zero, sizeof(int)))) return rc;
+    const char *q = (const char *)d_q[loc[s]] + s * n * real_size();
+    hipError_t e = launch_finite(precision, q, n, d_flag, stream);
+    if (e != hipSuccess) return hipfail(e, "finite kernel launch");
+    if ((rc = download(&flag, d_flag, sizeof(int)))) return rc;
+    if (flag)
+      return fail(DGW_ENONFINITE, "non-finite field value in shot " + std::to_string(s) +
+                                      " at step " + std::to_string(h_step[s]));
+  }
+  if (wd_growth <= 0) return DGW_OK;
+  if ((int)wd_energy.size() != nshots) wd_energy.assign(nshots, 0.0);
+  for (int s = 0; s < nshots; ++s) {
+    double E = 0;
+    const int rc = dgw_energy(this, s, &E);
+    if (rc) return rc;
+    if (wd_energy[s] > 0 && E > wd_growth * wd_energy[s]) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "energy of shot %d grew by a factor %.3g by step %lld", s,
+               E / wd_energy[s], (long long)h_step[s]);
+      wd_energy[s] = E;
+      return fail(DGW_EGROWTH, buf);
+    }
+    wd_energy[s] = E;
+  }
+  return DGW_OK;
+}
+
+int dgw_step(dgw_ctx *c, int64_t nsteps) {
+  if (!c) return DGW_EINVAL;
+  RoctxRange range("dgw_step");
+  int rc = DGW_OK;
+  if (c->wd_every <= 0 || nsteps <= 0) {
+    rc = step_core(c, nsteps);
+  } else {
+    // chunks ending where the watchdog checks; every chunk is an ordinary
+    // call, so the steps are the same as in one call
+    int64_t done = 0;
+    while (done < nsteps && rc == DGW_OK) {
+      const int64_t chunk = std::min(nsteps - done, c->wd_every - c->wd_since);
+      rc = step_core(c, chunk);
+      if (rc) break;
+      done += chunk;
+      c->wd_since += chunk;
+      if (c->wd_since >= c->wd_every) {
+        c->wd_since = 0;
+        rc = c->watchdog_check();
+      }
+    }
+  }
+  return rc;
+}
+
+int dgw_set_watchdog(dgw_ctx *c, int64_t every, double max_growth) {
+  if (!c) return DGW_EINVAL;
+  if (every < 0) return c->fail(DGW_EINVAL, "negative watchdog interval");
+  if (!std::isfinite(max_growth) || max_growth < 0 || (max_growth > 0 && max_growth < 1))
+    return c->fail(DGW_EINVAL, "watchdog growth bound must be 0 or a finite value >= 1");
+  c->wd_every = every;
+  c->wd_growth = max_growth;
+  c->wd_since = 0;
+  c->wd_energy.assign(c->nshots, 0.0);
   return DGW_OK;
 }
 

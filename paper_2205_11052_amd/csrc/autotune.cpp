@@ -69,6 +69,7 @@ struct Shape {
 extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *kernel,
                             int *elems_per_block, int *wgs_per_cu) {
   if (!c) return DGW_EINVAL;
+  RoctxRange range("dgw_autotune");
   if (!c->have_mesh || !c->have_mat || !c->have_dt)
     return c->fail(DGW_ESTATE, "mesh, material and dt must be set first");
   char key[128];

@@ -8,6 +8,16 @@
 
 #include "dgw_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
+// A roctx range over a scope (rocprofv3 --marker-trace shows it).
+struct RoctxRange {
+  explicit RoctxRange(const char *name) { roctxRangePushA(name); }
+  ~RoctxRange() { roctxRangePop(); }
+  RoctxRange(const RoctxRange &) = delete;
+  RoctxRange &operator=(const RoctxRange &) = delete;
+};
+
 namespace dgw {
 const double *rk_a();
 const double *rk_b();
@@ -98,6 +108,15 @@ struct dgw_ctx {
   // reverse sweep refuses to run when it has moved.
   uint64_t gen = 0;
   void touch() { ++gen; }
+
+  // step watchdog (dgw_set_watchdog): check every wd_every steps, energy
+  // bound factor wd_growth (0: finiteness only), steps since the last check,
+  // each shot's energy at the last check (0: no baseline)
+  int64_t wd_every = 0;
+  double wd_growth = 0;
+  int64_t wd_since = 0;
+  std::vector<double> wd_energy;
+  int watchdog_check();
 
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;

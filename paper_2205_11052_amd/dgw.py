@@ -302,6 +302,13 @@ class Solver:
     def check_finite(self):
         self._check(self.lib.dgw_check_finite(self._ctx), "dgw_check_finite")
 
+    def set_watchdog(self, every, max_growth=0.0):
+        """Check the fields every `every` steps of dgw_step (0: off): NaN or
+        infinity raises DGW_ENONFINITE, and with max_growth > 0 an energy
+        rise by more than that factor between checks raises DGW_EGROWTH."""
+        self._check(self.lib.dgw_set_watchdog(self._ctx, int(every), float(max_growth)),
+                    "dgw_set_watchdog")
+
     # -- differentiation --------------------------------------------------
     def forward_checkpointed(self, nsteps, ckpt_every, d_obs):
         d = _host64(d_obs)
