@@ -11,8 +11,8 @@ derivative d/dx_b is replaced by d/dx_b + (memory variable), the memory
 variable of a derivative du/dx_b obeying
     m_t = -(d_b + alpha_b) m - d_b du/dx_b,
 with d_b >= 0 the damping profile and alpha_b >= 0 the frequency shift of
-axis b (both constant per element here; where d_b = 0 a memory variable that
-starts at zero stays zero).  For the velocity-stress system this gives
+axis b (given per element [K, 3] or per node [K, 3, Np]; where d_b = 0 a
+memory variable that starts at zero stays zero).  For the velocity-stress system this gives
     rho v_c,t = sum_b (D_cb + phi_cb),
     sigma_t   = lambda tr(G + Psi) I + mu (G + Psi + (G + Psi)^T),
     phi_cb,t  = -(d_b + alpha_b) phi_cb - d_b D_cb,
@@ -99,7 +99,8 @@ def layer_terms(m, rho, lam, mu):
 
 
 def memory_rate(P, q, m, rho, lam, mu, d, alpha):
-    """m_t [K, 18, Np] for the damping profile d and shift alpha [K, 3]."""
+    """m_t [K, 18, Np] for the damping profile d and shift alpha, per element
+    [K, 3] or per node [K, 3, Np]."""
     D, G = directional(P, q, rho, lam, mu)
     # d_b, alpha_b per element [K, 3] or per node [K, 3, Np]
     ex = (lambda a: a[:, None, :, None]) if d.dim() == 2 else (lambda a: a[:, None])
