@@ -258,7 +258,7 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
     tmp.clear();
   };
   void *lq = alloc(n), *lr = alloc(n), *res = alloc(n);
-  void *zbuf = alloc((size_t)c->nshots * K * 9 * NF * rs);
+  void *zbuf = alloc((size_t)c->nshots * K * 7 * NF * rs);
   double *grad = (double *)alloc(sizeof(double) * c->nshots * K * 3);
   // Keep the four inner stage states of every step of a segment when the
   // memory budget allows (every x 4 more states): the segment recompute

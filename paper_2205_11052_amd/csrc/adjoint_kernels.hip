@@ -6,7 +6,10 @@
 // stage is   lam_q += dt L^T w,   lam_r = a w,   g += dt (d(Lq)/dm)^T w.
 // It runs as two launches:
 //   adj_lift_kernel: z_f = Fscale_f LIFT_f^T w on every face node (9
-//       components), stored per element and face node;
+//       components), stored per element and face node as the seven
+//       combinations the flux transpose uses, with the element's own 1/rho
+//       and outward normal: a = z_v / rho (3), c = Zt n (3) with
+//       Zt = diag(2 z_xx, 2 z_yy, 2 z_zz) + the off-diagonal z_s, and tr z_s;
 //   adj_main_kernel: per face node the transpose of the Riemann flux, taking
 //       the own z for the own side and the neighbour's z (at the matched
 //       node) for the neighbour's flux, which also depends on this
@@ -45,16 +48,17 @@ template <> struct AdjBlock<6> { static constexpr int be = 2; };
 constexpr int kT = 256;
 
 // Adjoint of the face flux for one side.  Inputs: n, jumps as seen from this
-// side, material of this side (ri = 1/rho, la, mu, zp, zs), impedances of the
-// other side (zpo, zso), izp, izs, and z (9 components, Voigt order).
+// side, material of this side (la, mu, zp, zs), impedances of the other side
+// (zpo, zso), izp, izs, and the side's lifted adjoint as its seven
+// combinations zc = (a = z_v / rho, c = Zt n, tr z_s).
 // Outputs: Jv, Jt (adjoint of the jumps [v] and [t]); dZpm, dZpo, dZsm, dZso
 // (derivatives of z . flux w.r.t. this side's and the other side's
 // impedances); and the forward dv, dt (for the explicit gradient terms).
 template <typename real>
 __device__ inline void flux_adjoint(
-    const real n[3], const real jv[3], const real jt[3], real ri, real la,
+    const real n[3], const real jv[3], const real jt[3], real la,
     real mu, real zp, real zs, real zpo, real zso, real izp, real izs,
-    const real z[9], real Jv[3], real Jt[3], real &dZpm, real &dZpo,
+    const real zc[7], real Jv[3], real Jt[3], real &dZpm, real &dZpo,
     real &dZsm, real &dZso, real dv[3], real dtr[3]) {
   const real jvn = jv[0] * n[0] + jv[1] * n[1] + jv[2] * n[2];
   const real jtn = jt[0] * n[0] + jt[1] * n[1] + jt[2] * n[2];
@@ -71,15 +75,15 @@ __device__ inline void flux_adjoint(
     dv[a] = kn * n[a] + kTv[a];
     dtr[a] = zp * kn * n[a] + zs * kTv[a];
   }
-  // a = z_v / rho ; b = lambda tr(z_s) n + mu Zfull n
-  const real trz = z[3] + z[4] + z[5];
+  // a = z_v / rho ; b = lambda tr(z_s) n + mu Zt n
+  const real trz = zc[6];
   real av[3], bv[3];
-  av[0] = ri * z[0];
-  av[1] = ri * z[1];
-  av[2] = ri * z[2];
-  bv[0] = la * trz * n[0] + mu * (2 * z[3] * n[0] + z[8] * n[1] + z[7] * n[2]);
-  bv[1] = la * trz * n[1] + mu * (z[8] * n[0] + 2 * z[4] * n[1] + z[6] * n[2]);
-  bv[2] = la * trz * n[2] + mu * (z[7] * n[0] + z[6] * n[1] + 2 * z[5] * n[2]);
+  av[0] = zc[0];
+  av[1] = zc[1];
+  av[2] = zc[2];
+  bv[0] = la * trz * n[0] + mu * zc[3];
+  bv[1] = la * trz * n[1] + mu * zc[4];
+  bv[2] = la * trz * n[2] + mu * zc[5];
   const real an = av[0] * n[0] + av[1] * n[1] + av[2] * n[2];
   const real bn = bv[0] * n[0] + bv[1] * n[1] + bv[2] * n[2];
   const real alpha = bn + zp * an;
@@ -109,6 +113,7 @@ __global__ void __launch_bounds__(kT) adj_lift_kernel(AdjArgs<real> A) {
   constexpr int Np = SzA<N>::Np, Nfp = SzA<N>::Nfp, NF = 4 * Nfp;
   __shared__ real sw[BE * 9 * Np];
   __shared__ double sfs[BE * 4];
+  __shared__ double sgeo[BE * 13];   // 1/rho and the four outward normals
   const int shot = blockIdx.y;
   const int64_t k0 = (int64_t)blockIdx.x * BE;
   if (k0 >= A.K) return;   // never taken (the grid covers the mesh exactly)
@@ -143,6 +148,14 @@ __global__ void __launch_bounds__(kT) adj_lift_kernel(AdjArgs<real> A) {
       const int t = tid + u * kT, tt = t < nE * 4 ? t : 0;
       fsv[u] = A.meta[(k0 + tt / 4) * DGW_META + M_FSCALE + (tt & 3)];
     }
+    constexpr int GV = (BE * 13 + kT - 1) / kT;
+    double gv[GV];
+#pragma unroll
+    for (int u = 0; u < GV; ++u) {
+      const int t = tid + u * kT, tt = t < nE * 13 ? t : 0;
+      const int e = tt / 13, j = tt - 13 * e;
+      gv[u] = A.meta[(k0 + e) * DGW_META + (j == 0 ? M_RHOINV : M_NORMAL + j - 1)];
+    }
     const int64_t step = A.shot_step[shot];
     if (step >= A.shot_len[shot]) return;   // uniform per work-group
 #pragma unroll
@@ -161,9 +174,14 @@ __global__ void __launch_bounds__(kT) adj_lift_kernel(AdjArgs<real> A) {
       const int t = tid + u * kT;
       if (t < nE * 4) sfs[t] = fsv[u];
     }
+#pragma unroll
+    for (int u = 0; u < GV; ++u) {
+      const int t = tid + u * kT;
+      if (t < nE * 13) sgeo[t] = gv[u];
+    }
   }
   __syncthreads();
-  real *zb = A.zbuf + (shot * A.K + k0) * 9 * NF;
+  real *zb = A.zbuf + (shot * A.K + k0) * 7 * NF;
   for (int t = threadIdx.x; t < nE * NF; t += kT) {
     const int e = t / NF, fm = t - e * NF;
     const real *we = sw + e * 9 * Np;
@@ -175,9 +193,24 @@ __global__ void __launch_bounds__(kT) adj_lift_kernel(AdjArgs<real> A) {
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[c] += l * we[c * Np + i];
     }
-    const real fs = (real)sfs[e * 4 + fm / Nfp];
+    const int f = fm / Nfp;
+    const real fs = (real)sfs[e * 4 + f];
+    real z[9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) zb[(e * 9 + c) * NF + fm] = fs * acc[c];
+    for (int c = 0; c < 9; ++c) z[c] = fs * acc[c];
+    const double *ge = sgeo + e * 13;
+    const real ri = (real)ge[0];
+    const real n0 = (real)ge[1 + 3 * f], n1 = (real)ge[2 + 3 * f], n2 = (real)ge[3 + 3 * f];
+    real zc[7];
+    zc[0] = ri * z[0];
+    zc[1] = ri * z[1];
+    zc[2] = ri * z[2];
+    zc[3] = 2 * z[3] * n0 + z[8] * n1 + z[7] * n2;
+    zc[4] = z[8] * n0 + 2 * z[4] * n1 + z[6] * n2;
+    zc[5] = z[7] * n0 + z[6] * n1 + 2 * z[5] * n2;
+    zc[6] = z[3] + z[4] + z[5];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) zb[(e * 7 + c) * NF + fm] = zc[c];
   }
 }
 
@@ -199,7 +232,7 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
   const real *__restrict__ q = A.q + soff;
   real *lq = A.lam_q + soff;
   real *lr = A.lam_r + soff;
-  const real *zb = A.zbuf + shot * A.K * 9 * NF;
+  const real *zb = A.zbuf + shot * A.K * 7 * NF;
   const real b = (real)A.rk_b;
   const int tid = threadIdx.x;
 
@@ -210,7 +243,7 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
   constexpr int FI = (BE * NF + kT - 1) / kT;   // face items per thread
   // level 1: this thread's face tables and own z
   int cnv[FI], n1v[FI], n2v[FI], f2v[FI];
-  real zo[FI][9];
+  real zo[FI][7];
 #pragma unroll
   for (int u = 0; u < FI; ++u) {
     const int t = tid + u * kT;
@@ -224,7 +257,7 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
     n2v[u] = A.nbnode[k * NF + fm];
     f2v[u] = A.nbfnode[k * NF + fm];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) zo[u][c] = zb[(k * 9 + c) * NF + fm];
+    for (int c = 0; c < 7; ++c) zo[u][c] = zb[(k * 7 + c) * NF + fm];
   }
   // the block's w = lam_r + b lam_q and stage input q (16-byte vectors over
   // its contiguous span) and per-element data
@@ -258,21 +291,19 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
   if (step >= A.shot_len[shot]) return;   // uniform per work-group
   // level 2: the neighbour's trace, z at the matched face node and material
   // (element 0 where the face has no neighbour; never used)
-  real qp[FI][9], zn[FI][9], gn[FI][5];
+  real qp[FI][9], zn[FI][7], gn[FI][4];
 #pragma unroll
   for (int u = 0; u < FI; ++u) {
     const int64_t nb = cnv[u] >= 0 ? (int64_t)(cnv[u] >> 5) : 0;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      qp[u][c] = q[(nb * 9 + c) * Np + n2v[u]];
-      zn[u][c] = zb[(nb * 9 + c) * NF + f2v[u]];
-    }
+    for (int c = 0; c < 9; ++c) qp[u][c] = q[(nb * 9 + c) * Np + n2v[u]];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) zn[u][c] = zb[(nb * 7 + c) * NF + f2v[u]];
     const double *g2 = A.meta + nb * DGW_META;
-    gn[u][0] = (real)g2[M_RHOINV];
-    gn[u][1] = (real)g2[M_LAM];
-    gn[u][2] = (real)g2[M_MU];
-    gn[u][3] = (real)g2[M_ZP];
-    gn[u][4] = (real)g2[M_ZS];
+    gn[u][0] = (real)g2[M_LAM];
+    gn[u][1] = (real)g2[M_MU];
+    gn[u][2] = (real)g2[M_ZP];
+    gn[u][3] = (real)g2[M_ZS];
   }
   // the block's values to LDS
 #pragma unroll
@@ -346,7 +377,7 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
     const real zpo = (real)g[M_ZPNB + f], zso = (real)g[M_ZSNB + f];
     const real izp = (real)g[M_IZPS + f], izs = (real)g[M_IZSS + f];
     real Jv[3], Jt[3], dv[3], dtr[3], dZpm, dZpo, dZsm, dZso;
-    flux_adjoint<real>(n, jv, jt, ri, la, mu, zp, zs, zpo, zso, izp, izs, z,
+    flux_adjoint<real>(n, jv, jt, la, mu, zp, zs, zpo, zso, izp, izs, z,
                        Jv, Jt, dZpm, dZpo, dZsm, dZso, dv, dtr);
     // adjoint of sigma from [t] = [sigma] n (Voigt xx yy zz yz xz xy)
     real Js[6];
@@ -369,14 +400,13 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
 #pragma unroll
       for (int a = 0; a < 6; ++a) out[3 + a] = -Js[a];
     }
-    // explicit material factors of the own flux
+    // explicit material factors of the own flux: with a = z_v / rho,
+    // d/d(1/rho) is z_v . dt = rho a . dt (so d/drho is -(1/rho) a . dt),
+    // d/dlambda is tr z_s (n . dv), d/dmu is dv . Zt n
     const real ndv = n[0] * dv[0] + n[1] * dv[1] + n[2] * dv[2];
-    double gr = -(double)ri * (double)(ri * (z[0] * dtr[0] + z[1] * dtr[1] + z[2] * dtr[2]));
-    double gl = (double)(z[3] + z[4] + z[5]) * (double)ndv;
-    double gm = (double)(2 * (z[3] * dv[0] * n[0] + z[4] * dv[1] * n[1] + z[5] * dv[2] * n[2]) +
-                         z[6] * (dv[1] * n[2] + dv[2] * n[1]) +
-                         z[7] * (dv[0] * n[2] + dv[2] * n[0]) +
-                         z[8] * (dv[0] * n[1] + dv[1] * n[0]));
+    double gr = -(double)ri * (double)(z[0] * dtr[0] + z[1] * dtr[1] + z[2] * dtr[2]);
+    double gl = (double)z[6] * (double)ndv;
+    double gm = (double)(z[3] * dv[0] + z[4] * dv[1] + z[5] * dv[2]);
     double dzp = dZpm, dzs = dZsm;
     if (cn < 0) {
       dzp += dZpo;   // boundary: the ghost impedance is the own impedance
@@ -387,7 +417,7 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
       real nn[3] = {-n[0], -n[1], -n[2]};
       real jvn[3] = {-jv[0], -jv[1], -jv[2]};
       real Jv2[3], Jt2[3], dv2[3], dt2[3], a1, a2, a3, a4;
-      flux_adjoint<real>(nn, jvn, jt, gn[u][0], gn[u][1], gn[u][2], gn[u][3], gn[u][4],
+      flux_adjoint<real>(nn, jvn, jt, gn[u][0], gn[u][1], gn[u][2], gn[u][3],
                          zp, zs, izp, izs, zn[u], Jv2, Jt2, a1, a2, a3, a4, dv2, dt2);
       // this element is the neighbour's "+" side: [v]' = v_k - v_nb etc.
       out[0] += Jv2[0];

@@ -183,7 +183,7 @@ template <typename real>
 struct AdjArgs {
   const real *q;                // stage input state
   real *lam_q, *lam_r;          // adjoint of q and of res
-  real *zbuf;                   // [S][K][9][4 Nfp] Fscale LIFT^T w
+  real *zbuf;                   // [S][K][7][4 Nfp] combinations of Fscale LIFT^T w
   double *grad;                 // [S][K][3] (rho, lambda, mu)
   const double *meta;
   const int32_t *conn;
