@@ -82,11 +82,16 @@ int upload_adjoint_tables(dgw_ctx *c) {
 
 template <typename real>
 void fill_adj(dgw_ctx *c, AdjArgs<real> &a, const void *q, void *lq, void *lr,
-              void *zbuf, double *grad, int stage) {
+              void *zbuf, void *zbuf_next, double *grad, int stage) {
   a.q = (const real *)q;
   a.lam_q = (real *)lq;
   a.lam_r = (real *)lr;
   a.zbuf = (real *)zbuf;
+  // stages 4..1 of a step form the lifted adjoint of the next reverse stage
+  // (stage - 1); stage 0 is followed by the next step's injection
+  a.zbuf_next = (real *)zbuf_next;
+  a.lift_next = stage > 0 ? 1 : 0;
+  a.next_b = stage > 0 ? rk_b()[stage - 1] : 0.0;
   a.grad = grad;
   a.meta = c->d_meta;
   a.conn = c->d_conn;
@@ -258,7 +263,9 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
     tmp.clear();
   };
   void *lq = alloc(n), *lr = alloc(n), *res = alloc(n);
+  // lifted adjoint of the current reverse stage and of the next one
   void *zbuf = alloc((size_t)c->nshots * K * 7 * NF * rs);
+  void *zbuf2 = alloc((size_t)c->nshots * K * 7 * NF * rs);
   double *grad = (double *)alloc(sizeof(double) * c->nshots * K * 3);
   // Keep the four inner stage states of every step of a segment when the
   // memory budget allows (every x 4 more states): the segment recompute
@@ -279,7 +286,7 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
     for (int i = 1; i < 5; ++i) st[i] = alloc(n);
   std::vector<void *> seg;
   for (int64_t i = 0; i < a->every * per_step; ++i) seg.push_back(alloc(n));
-  bool ok = lq && lr && res && zbuf && grad;
+  bool ok = lq && lr && res && zbuf && zbuf2 && grad;
   if (!keep) ok = ok && st[1] && st[2] && st[3] && st[4];
   for (void *p : seg) ok = ok && p;
   if (!ok) {
@@ -348,18 +355,23 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
         for (int i = 0; i < 4 && rc == DGW_OK; ++i)
           rc = stage_explicit(c, sx[i], sx[i + 1], res, i);
       }
+      // the step's first reverse stage lifts w itself (after the
+      // injection); each later one reads what the previous main kernel
+      // formed, the two buffers alternating
+      void *zc = zbuf, *zx = zbuf2;
       for (int i = 4; i >= 0 && rc == DGW_OK; --i) {
         const bool tm = c->timing && timed_used + 2 <= (int)c->adj_ev.size();
         if (tm) (void)hipEventRecord(c->adj_ev[timed_used], c->stream);
         if (c->precision == 64) {
           AdjArgs<double> aa;
-          fill_adj(c, aa, sx[i], lq, lr, zbuf, grad, i);
-          e = launch_adjoint_stage(c->R.N, 64, c->nshots, &aa, c->stream);
+          fill_adj(c, aa, sx[i], lq, lr, zc, zx, grad, i);
+          e = launch_adjoint_stage(c->R.N, 64, c->nshots, &aa, i == 4, c->stream);
         } else {
           AdjArgs<float> aa;
-          fill_adj(c, aa, sx[i], lq, lr, zbuf, grad, i);
-          e = launch_adjoint_stage(c->R.N, 32, c->nshots, &aa, c->stream);
+          fill_adj(c, aa, sx[i], lq, lr, zc, zx, grad, i);
+          e = launch_adjoint_stage(c->R.N, 32, c->nshots, &aa, i == 4, c->stream);
         }
+        std::swap(zc, zx);
         if (e != hipSuccess) rc = c->hipfail(e, "adjoint stage launch");
         if (tm) {
           (void)hipEventRecord(c->adj_ev[timed_used + 1], c->stream);

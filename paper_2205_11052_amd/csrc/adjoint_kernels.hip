@@ -16,6 +16,12 @@
 //       element's trace and impedances; per node the transpose of the
 //       volume operator; the gradient from the explicit 1/rho, lambda, mu
 //       factors and from the impedances of both sides of every face.
+// Within a step the lift kernel runs only for the first reverse stage: each
+// main kernel ends by forming the next stage's lifted adjoint from its own
+// updated lam_r + b' lam_q (the next stage's w, complete once this stage has
+// run, since nothing else touches lam between two stages of a step), into a
+// second buffer.  Before a step's first reverse stage the receiver residual
+// is injected into lam_q, so that stage lifts afresh.
 // Notation (own side "-", neighbour "+", n the own outward normal):
 //   [v] = v+ - v-, [t] = (sigma+ - sigma-) n,
 //   kn = (n.[t] + Zp+ n.[v]) / (Zp- + Zp+),
@@ -553,14 +559,54 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
       }
     }
     const real rdt = (real)A.dt, ra = (real)A.rk_a;
+    const real nb_ = (real)A.next_b;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       const int64_t idx = (k * 9 + c) * Np + i;
-      lq[idx] += rdt * adj[c];
-      lr[idx] = ra * we[c * Np + i];
+      const real lqn = lq[idx] + rdt * adj[c];
+      const real lrn = ra * we[c * Np + i];
+      lq[idx] = lqn;
+      lr[idx] = lrn;
+      // the next stage's w at this node, over this node's own entry of the
+      // stage input (read above by this thread only)
+      if (A.lift_next) sq[e * 9 * Np + c * Np + i] = lrn + nb_ * lqn;
     }
   }
   __syncthreads();
+  // ---- the next reverse stage's lifted adjoint (as adj_lift_kernel) ----
+  if (A.lift_next) {
+    real *zn_ = A.zbuf_next + (shot * A.K + k0) * 7 * NF;
+    for (int t = tid; t < nE * NF; t += kT) {
+      const int e = t / NF, fm = t - e * NF, f = fm / Nfp;
+      const real *we = sq + e * 9 * Np;
+      const double *g = smeta + e * DGW_META;
+      real acc[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[c] = 0;
+      for (int i = 0; i < Np; ++i) {
+        const real l = A.LIFT[i * NF + fm];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[c] += l * we[c * Np + i];
+      }
+      const real fs = (real)g[M_FSCALE + f];
+      real z[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) z[c] = fs * acc[c];
+      const real ri = (real)g[M_RHOINV];
+      const real n0 = (real)g[M_NORMAL + 3 * f], n1 = (real)g[M_NORMAL + 3 * f + 1],
+                 n2 = (real)g[M_NORMAL + 3 * f + 2];
+      real zc[7];
+      zc[0] = ri * z[0];
+      zc[1] = ri * z[1];
+      zc[2] = ri * z[2];
+      zc[3] = 2 * z[3] * n0 + z[8] * n1 + z[7] * n2;
+      zc[4] = z[8] * n0 + 2 * z[4] * n1 + z[6] * n2;
+      zc[5] = z[7] * n0 + z[6] * n1 + 2 * z[5] * n2;
+      zc[6] = z[3] + z[4] + z[5];
+#pragma unroll
+      for (int c = 0; c < 7; ++c) zn_[(e * 7 + c) * NF + fm] = zc[c];
+    }
+  }
   // ---- per-element gradient reduction (FP64) --------------------------
   for (int t = tid; t < nE * 3; t += kT) {
     const int e = t / 3, p = t - 3 * e;
@@ -603,26 +649,28 @@ __global__ void set_steps_kernel(int64_t *steps, int n, int64_t value) {
 }
 
 template <int N, typename real>
-hipError_t adj_launch_t(int nshots, const AdjArgs<real> &a, hipStream_t st) {
+hipError_t adj_launch_t(int nshots, const AdjArgs<real> &a, bool lift, hipStream_t st) {
   constexpr int BE = AdjBlock<N>::be;
   dim3 grid((unsigned)((a.K + BE - 1) / BE), (unsigned)nshots);
-  hipLaunchKernelGGL((adj_lift_kernel<N, real, BE>), grid, dim3(kT), 0, st, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (lift) {
+    hipLaunchKernelGGL((adj_lift_kernel<N, real, BE>), grid, dim3(kT), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL((adj_main_kernel<N, real, BE>), grid, dim3(kT), 0, st, a);
   return hipGetLastError();
 }
 
 template <typename real>
-hipError_t adj_launch_r(int N, int nshots, const void *args, hipStream_t st) {
+hipError_t adj_launch_r(int N, int nshots, const void *args, bool lift, hipStream_t st) {
   const AdjArgs<real> &a = *(const AdjArgs<real> *)args;
   switch (N) {
-    case 1: return adj_launch_t<1, real>(nshots, a, st);
-    case 2: return adj_launch_t<2, real>(nshots, a, st);
-    case 3: return adj_launch_t<3, real>(nshots, a, st);
-    case 4: return adj_launch_t<4, real>(nshots, a, st);
-    case 5: return adj_launch_t<5, real>(nshots, a, st);
-    case 6: return adj_launch_t<6, real>(nshots, a, st);
+    case 1: return adj_launch_t<1, real>(nshots, a, lift, st);
+    case 2: return adj_launch_t<2, real>(nshots, a, lift, st);
+    case 3: return adj_launch_t<3, real>(nshots, a, lift, st);
+    case 4: return adj_launch_t<4, real>(nshots, a, lift, st);
+    case 5: return adj_launch_t<5, real>(nshots, a, lift, st);
+    case 6: return adj_launch_t<6, real>(nshots, a, lift, st);
   }
   return hipErrorInvalidValue;
 }
@@ -630,9 +678,9 @@ hipError_t adj_launch_r(int N, int nshots, const void *args, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_adjoint_stage(int N, int precision, int nshots,
-                                const void *args, hipStream_t st) {
-  if (precision == 64) return adj_launch_r<double>(N, nshots, args, st);
-  return adj_launch_r<float>(N, nshots, args, st);
+                                const void *args, bool lift, hipStream_t st) {
+  if (precision == 64) return adj_launch_r<double>(N, nshots, args, lift, st);
+  return adj_launch_r<float>(N, nshots, args, lift, st);
 }
 
 hipError_t launch_inject(int precision, int nshots, int Np, void *lam_q,

@@ -184,6 +184,11 @@ struct AdjArgs {
   const real *q;                // stage input state
   real *lam_q, *lam_r;          // adjoint of q and of res
   real *zbuf;                   // [S][K][7][4 Nfp] combinations of Fscale LIFT^T w
+  // with lift_next set, the main kernel also forms the next reverse stage's
+  // lifted adjoint from its updated lam_r + next_b lam_q into zbuf_next
+  real *zbuf_next;
+  double next_b;
+  int lift_next;
   double *grad;                 // [S][K][3] (rho, lambda, mu)
   const double *meta;
   const int32_t *conn;
@@ -203,8 +208,10 @@ struct AdjArgs {
 };
 
 // Launchers (adjoint_kernels.hip).
+// lift: launch the lift kernel first (else zbuf already holds the stage's
+// lifted adjoint, formed by the previous stage's main kernel)
 hipError_t launch_adjoint_stage(int N, int precision, int nshots,
-                                const void *args, hipStream_t st);
+                                const void *args, bool lift, hipStream_t st);
 // lam_q[k_r][c][j] += dt w_r[j] (trace[r][c][step] - d_obs[r][c][step])
 hipError_t launch_inject(int precision, int nshots, int Np, void *lam_q,
                          int64_t shot_stride, const int32_t *nrec, int rmax,
