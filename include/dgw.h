@@ -142,6 +142,15 @@ int dgw_set_receivers(dgw_ctx *ctx, int shot, int nrec, const double *xyz,
 int dgw_set_fields(dgw_ctx *ctx, int shot, const double *q);
 int dgw_get_fields(dgw_ctx *ctx, int shot, double *q);
 
+/* Resume a shot at its own time: set its step counter to `step` (time
+ * step * dt for the source and the trace index), after dgw_set_fields has
+ * loaded the state saved at that step.  The shot's traces before `step` stay
+ * as dgw_set_fields left them (zero); the next dgw_step records from `step`
+ * on.  Memory variables of a perfectly matched layer are not part of the
+ * saved state: they restart at zero.  DGW_ERANGE for a shot out of range, a
+ * negative step, or a step beyond the shot's length. */
+int dgw_set_shot_step(dgw_ctx *ctx, int shot, int64_t step);
+
 /* Advance every shot that has steps left by up to nsteps steps (a shot stops
  * at its length).  Each step is five fused RHS + LSERK stage launches and one
  * receiver-sampling launch; batches of steps are replayed from a captured

@@ -35,6 +35,7 @@ SIGNATURES = {
     "dgw_set_receivers": (C.c_int, [_P, C.c_int, C.c_int, _D, _I64]),
     "dgw_set_fields": (C.c_int, [_P, C.c_int, _D]),
     "dgw_get_fields": (C.c_int, [_P, C.c_int, _D]),
+    "dgw_set_shot_step": (C.c_int, [_P, C.c_int, _I64]),
     "dgw_step": (C.c_int, [_P, _I64]),
     "dgw_read_traces": (C.c_int, [_P, C.c_int, _D, _I64, _PI64]),
     "dgw_shot_steps": (C.c_int, [_P, C.c_int, _PI64]),

@@ -779,6 +779,17 @@ int dgw_set_fields(dgw_ctx *c, int shot, const double *q) {
   return c->clear_traces(shot);
 }
 
+int dgw_set_shot_step(dgw_ctx *c, int shot, int64_t step) {
+  if (!c) return DGW_EINVAL;
+  if (!c->have_mesh) return c->fail(DGW_ESTATE, "set the mesh first");
+  if (shot < 0 || shot >= c->nshots) return c->fail(DGW_ERANGE, "shot out of range");
+  if (step < 0 || step > c->h_len[shot])
+    return c->fail(DGW_ERANGE, "step outside the shot's length");
+  c->touch();
+  c->h_step[shot] = step;
+  return c->upload(c->d_step + shot, &c->h_step[shot], sizeof(int64_t));
+}
+
 int dgw_get_fields(dgw_ctx *c, int shot, double *q) {
   if (!c) return DGW_EINVAL;
   if (!c->have_mesh) return c->fail(DGW_ESTATE, "set the mesh first");

@@ -257,6 +257,12 @@ class Solver:
         for s in range(self.nshots):
             self.set_fields(s, z)
 
+    def set_shot_step(self, shot, step):
+        """Resume shot `shot` at step `step` (after set_fields loaded the
+        state saved there)."""
+        self._check(self.lib.dgw_set_shot_step(self._ctx, int(shot), int(step)),
+                    "dgw_set_shot_step")
+
     def get_fields(self, shot):
         out = np.empty((self.K, 9, self.Np))
         self._check(self.lib.dgw_get_fields(self._ctx, shot, _dptr(out)),

@@ -421,6 +421,49 @@ def test_compacted_batch_with_graph_replays(kernel):
     b.close()
 
 
+def test_resume_at_own_time():
+    """A source-driven run saved at step 12 and resumed there
+    (dgw_set_fields, then dgw_set_shot_step) continues exactly as the
+    uninterrupted run: fields and the traces from step 12 on, bitwise."""
+    mesh = W.kuhn_cube(3, 1.0)
+    K = mesh["etov"].shape[0]
+    rho, lam, mu = _random_medium(K, 31)
+    N = 3
+    P = oracle_problem(mesh, N)
+    dt = P.suggest_dt(rho, lam, mu, 0.5)
+    src, rec = np.array([0.4, 0.45, 0.55]), np.array([[0.3, 0.6, 1.0], [0.7, 0.2, 0.5]])
+    say("case resume")
+
+    def solver():
+        s = gpu_solver(mesh, N, rho, lam, mu, dt, 64, kernel=1)
+        s.set_source(0, src, 8.0, 0.05, 1.0, nsteps=30)
+        s.set_receivers(0, rec, 30)
+        s.zero_fields()
+        return s
+
+    a = solver()
+    a.step(20)
+    b = solver()
+    b.step(12)
+    q12 = b.get_fields(0)
+    b.close()
+    c = solver()
+    c.set_fields(0, q12)
+    c.set_shot_step(0, 12)
+    c.step(8)
+    assert c.shot_steps(0) == 20
+    assert np.array_equal(c.get_fields(0), a.get_fields(0))
+    ta, tc = a.read_traces(0), c.read_traces(0)
+    assert np.array_equal(tc[:, :, 12:20], ta[:, :, 12:20])
+    assert not tc[:, :, :12].any()
+    for bad in (-1, 31):
+        with pytest.raises(DGWError) as e:
+            c.set_shot_step(0, bad)
+        assert e.value.code == -6
+    a.close()
+    c.close()
+
+
 def test_tiny_mesh_smaller_than_a_block_and_zero_steps():
     mesh = W.kuhn_cube(1, 1.0)
     K = mesh["etov"].shape[0]
