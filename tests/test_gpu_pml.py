@@ -2,8 +2,10 @@
 the oracle with the same per-node profile: fields, receiver traces and the
 layer's memory variables, FP64 relative L2 <= 1e-12, FP32 <= 1e-5, with each
 stage kernel as the main kernel, the blended flux, a sponge on top, fluid
-elements in the layer, a moment source and two shots; the full-size
-82944-element order-4 workload in the benchmark's launch shapes; a zero
+elements in the layer, a moment source and two shots; graph replays equal
+single steps and the oracle; uneven shot lengths (launches over the active
+shots only) equal single-shot runs; the full-size 82944-element order-4
+workload in the benchmark's launch shapes; a zero
 profile and a removed layer give the plain run bit for bit; setting a shot's
 fields restarts its memory variables; arguments are checked.
 """
@@ -121,6 +123,60 @@ def test_pml_two_shots():
         say("pml shot %d fields %.3e memory %.3e" % (i, err, merr))
         assert err <= 1e-12 and merr <= 1e-12
     s.close()
+
+
+def test_pml_graph_replay_and_uneven_shots():
+    """With the layer, 23 steps in one call (two captured-graph replays and
+    three eager steps) equal 23 single-step calls bitwise and match the
+    oracle; two shots of lengths 9 and 23 in one batch (the launches cover
+    only the active shot after step 9) equal their single-shot runs
+    bitwise."""
+    mesh = W.kuhn_cube(3, 1.0)
+    K = mesh["etov"].shape[0]
+    N = 3
+    elems, prof, d, a = _unit_layer(mesh, N)
+    rho, lam, mu = _random_medium(K, 12)
+    P = oracle_problem(mesh, N)
+    dt = P.suggest_dt(rho, lam, mu, 0.5)
+    q0 = [random_fields(K, P.Np, 80 + i) for i in range(2)]
+    say("case pml graph replay")
+
+    def single(q, nsteps, calls):
+        s = gpu_solver(mesh, N, rho, lam, mu, dt, kernel=1)
+        s.set_pml(elems, prof)
+        s.set_fields(0, q)
+        for n in calls:
+            s.step(n)
+        out = (s.get_fields(0), s.pml_memory(0))
+        s.close()
+        return out
+
+    g = single(q0[0], 23, [23])
+    e = single(q0[0], 23, [1] * 23)
+    assert np.array_equal(g[0], e[0]) and np.array_equal(g[1], e[1])
+    q_o, m_o, _ = _oracle(P, q0[0], rho, lam, mu, d, a, dt, 23)
+    err = rel_l2(g[0], q_o)
+    merr = rel_l2(g[1], m_o[elems])
+    say("pml 23 steps fields %.3e memory %.3e" % (err, merr))
+    assert err <= 1e-12 and merr <= 1e-12
+    b = gpu_solver(mesh, N, rho, lam, mu, dt, nshots=2, kernel=1)
+    b.set_pml(elems, prof)
+    lens = (9, 23)
+    for i in range(2):
+        b.set_source(i, np.array([0.4, 0.5, 0.6]), 3.0, 0.1, 1.0, nsteps=lens[i])
+        b.set_fields(i, q0[i])
+    b.step(23)
+    for i in range(2):
+        one = gpu_solver(mesh, N, rho, lam, mu, dt, kernel=1)
+        one.set_pml(elems, prof)
+        one.set_source(0, np.array([0.4, 0.5, 0.6]), 3.0, 0.1, 1.0, nsteps=lens[i])
+        one.set_fields(0, q0[i])
+        one.step(23)
+        assert b.shot_steps(i) == lens[i]
+        assert np.array_equal(b.get_fields(i), one.get_fields(0))
+        assert np.array_equal(b.pml_memory(i), one.pml_memory(0))
+        one.close()
+    b.close()
 
 
 def test_full_size_pml_fp64():
