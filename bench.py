@@ -64,9 +64,9 @@ ANI_BYTES = 120 * 8                # anisotropic per-element data (DGW_ANI doubl
 # is reported only while the kernel source hashes to the value it was
 # measured for and the same launch shape runs; otherwise traffic is null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "38170cf3f700a2aa267b6a8d992831bd5d7e4fd476058e117ddd14c5524fc2dc",
+    "kernel_source_sha256": "81f545a6233552b8d7ae415e1e5d93c8e7a880f4515db6e3189e32ebe0f1277c",
     "launch_shape": (1, 7, 0),
-    "bytes_per_launch": 983494758,
+    "bytes_per_launch": 983433728,
 }
 
 
@@ -84,7 +84,7 @@ def measured_traffic(shape):
 MEASURED_COUNTERS = {
     "kernel_source_sha256": MEASURED_TRAFFIC["kernel_source_sha256"],
     "launch_shape": MEASURED_TRAFFIC["launch_shape"],
-    "values": {"mfma_busy": 0.449, "valu_busy": 0.212, "wave_wait_frac": 0.269},
+    "values": {"mfma_busy": 0.445, "valu_busy": 0.210, "wave_wait_frac": 0.269},
 }
 
 
@@ -756,7 +756,9 @@ def main():
     if not args.no_forms:
         forms = {}
         with torch.cuda.stream(stream):
-            s32 = build_solver(w, 32, stream=stream.cuda_stream, shape=shape)
+            # the FP32 form's own autotuned shape (its block choices differ:
+            # two column tiles per wave fit its LDS)
+            s32 = build_solver(w, 32, stream=stream.cuda_stream)
             sec32, _ = timed_steps(torch, s32, stream, args.steps, args.warmup)
             k32, _ = kernel_avg_ms(s32)
             shape32 = s32.shape
@@ -778,7 +780,7 @@ def main():
         bsteps = max(10, args.steps // 10)
         with torch.cuda.stream(stream):
             sb = build_solver(w, 32, nshots=nb, stream=stream.cuda_stream,
-                              shots=(pos, lens), shape=shape)
+                              shots=(pos, lens), shape=shape32)
             secb, _ = timed_steps(torch, sb, stream, bsteps, 2)
             kb, _ = kernel_avg_ms(sb, 2)
             shapeb = sb.shape

@@ -91,6 +91,83 @@ __device__ __forceinline__ void phase3_mfma(const StageArgs<real> &A, const real
   real *rs = res + k0 * 9 * Np, *qo = qout + k0 * 9 * Np;
   v4 acc[NT > 4 ? 2 : 1][MT];
   int ntl = 0;
+  if constexpr (!AN && NT == 8) {
+    // eight column tiles: each wave takes tiles w and w + 4 and feeds both
+    // from every operator fragment it loads (two MFMA chains per fragment)
+    const real *q0v[2], *q1v[2], *q2v[2], *flv[2];
+    real cv[2][3][3];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int nt = (tid >> 6) + 4 * h;
+      const int col = nt * 16 + (lane & 15);
+      const bool cok = col < 9 * nE;
+      const int e = cok ? col / 9 : 0, k = cok ? col - 9 * (col / 9) : 0;
+      const real *qe = sq + e * 9 * Np;
+      const double *gm = smeta + e * DGW_META;
+      // the same packed column tables as the one-tile path below
+      constexpr uint64_t F0 = 0x001000783ull, F1 = 0x122111648ull, F2 = 0x210222567ull;
+      constexpr uint32_t X0 = 0x1a000u, X1 = 0x01555u, X2 = 0x2aaaau;
+      constexpr uint32_t S0 = 0x36d2200u, S1 = 0x36d1400u, S2 = 0x490a400u;
+      const int f0 = (int)((F0 >> (4 * k)) & 15), f1 = (int)((F1 >> (4 * k)) & 15),
+                f2 = (int)((F2 >> (4 * k)) & 15);
+      const real ri = (real)gm[M_RHOINV], la = (real)gm[M_LAM], mu = (real)gm[M_MU];
+      const real l2 = la + 2 * mu;
+      auto fac = [&](uint32_t S) -> real {
+        const int id = (int)((S >> (3 * k)) & 7);
+        return id == 0 ? ri : id == 1 ? l2 : id == 2 ? la : id == 3 ? mu : (real)0;
+      };
+      const real s0 = fac(S0), s1 = fac(S1), s2 = fac(S2);
+      const int x0 = (int)((X0 >> (2 * k)) & 3), x1 = (int)((X1 >> (2 * k)) & 3),
+                x2 = (int)((X2 >> (2 * k)) & 3);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const real r0 = (real)gm[M_XINV + 3 * a], r1 = (real)gm[M_XINV + 3 * a + 1],
+                   r2 = (real)gm[M_XINV + 3 * a + 2];
+        auto pick = [&](int x) { return x == 0 ? r0 : x == 1 ? r1 : r2; };
+        cv[h][a][0] = s0 * pick(x0);
+        cv[h][a][1] = s1 * pick(x1);
+        cv[h][a][2] = s2 * pick(x2);
+      }
+      q0v[h] = qe + f0 * Np;
+      q1v[h] = qe + f1 * Np;
+      q2v[h] = qe + f2 * Np;
+      flv[h] = sfl + (e * 9 + k) * NF;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[h][mt] = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const real *Ab = A.Avol + (size_t)a * KS * MT * 64 + lane + oz;
+      for (int ks = 0; ks < KS; ++ks) {
+        const int j = 4 * ks + g, jj = j < Np ? j : Np - 1;
+        real b[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const real v = cv[h][a][0] * q0v[h][jj] + cv[h][a][1] * q1v[h][jj] +
+                         cv[h][a][2] * q2v[h][jj];
+          b[h] = j < Np ? v : (real)0;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const real af = Ab[(ks * MT + mt) * 64];
+          acc[0][mt] = M::mma(af, b[0], acc[0][mt]);
+          acc[1][mt] = M::mma(af, b[1], acc[1][mt]);
+        }
+      }
+    }
+    const real *Al = A.Alift + lane + oz;
+    for (int ks = 0; ks < KL; ++ks) {
+      const real b0 = flv[0][4 * ks + g], b1 = flv[1][4 * ks + g];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const real af = Al[(ks * MT + mt) * 64];
+        acc[0][mt] = M::mma(af, b0, acc[0][mt]);
+        acc[1][mt] = M::mma(af, b1, acc[1][mt]);
+      }
+    }
+  } else
   for (int nt = tid >> 6; nt < NT; nt += kThreads / 64, ++ntl) {
     const int col = nt * 16 + (lane & 15);
     const bool cok = col < 9 * nE;
@@ -783,8 +860,12 @@ struct Shapes {
   static constexpr int cap1 =
       V == 0 || V == 2 ? kThreads / Np : kThreads / 64 * 16 / 9;
   static constexpr int cap2 = 65536 / per;
-  static constexpr int a = cap1 < cap2 ? cap1 : cap2;
-  static constexpr int b = a / 2 > 0 ? a / 2 : 1;
+  static constexpr int a0 = cap1 < cap2 ? cap1 : cap2;
+  // isotropic matrix-core FP32: two column tiles per wave (14 elements) where
+  // the LDS tile fits, and the one-tile block as the second choice
+  static constexpr bool two = V == 1 && sizeof(real) == 4 && cap2 >= 2 * cap1;
+  static constexpr int a = two ? 2 * cap1 : a0;
+  static constexpr int b = two ? cap1 : (a0 / 2 > 0 ? a0 / 2 : 1);
 };
 
 template <int N, typename real, int BE, int V>

@@ -166,7 +166,9 @@ def test_full_size_layered_fp32_bench_launch(kernel):
     s = gpu_solver(w["mesh"], w["N"], w["rho"], w["lam"], w["mu"], dt, 32)
     s.set_source(0, w["source"], w["f0"], 0.05, w["amp"])
     s.set_receivers(0, w["receivers"], 8)
-    for be in ((7, 3) if kernel < 2 else (32,)):
+    # the FP32 block choices: kernel 0 (7, 3), kernel 1 (14, 7: two column
+    # tiles per wave, then one), kernel 2 (32)
+    for be in {0: (7, 3), 1: (14, 7), 2: (32,)}[kernel]:
         s.set_launch(kernel, be, 0)
         s.set_fields(0, q0)
         s.step(2)
