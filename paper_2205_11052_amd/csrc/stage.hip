@@ -861,9 +861,11 @@ struct Shapes {
       V == 0 || V == 2 ? kThreads / Np : kThreads / 64 * 16 / 9;
   static constexpr int cap2 = 65536 / per;
   static constexpr int a0 = cap1 < cap2 ? cap1 : cap2;
-  // isotropic matrix-core FP32: two column tiles per wave (14 elements) where
-  // the LDS tile fits, and the one-tile block as the second choice
-  static constexpr bool two = V == 1 && sizeof(real) == 4 && cap2 >= 2 * cap1;
+  // matrix-core FP32: two column tiles per wave (14 elements) where the LDS
+  // tile fits, and the one-tile block as the second choice (the isotropic
+  // form feeds both tiles from each operator fragment, the anisotropic form
+  // runs them one after the other); the two share their block choices
+  static constexpr bool two = (V == 1 || V == 3) && sizeof(real) == 4 && cap2 >= 2 * cap1;
   static constexpr int a = two ? 2 * cap1 : a0;
   static constexpr int b = two ? cap1 : (a0 / 2 > 0 ? a0 / 2 : 1);
 };
