@@ -146,8 +146,8 @@ int dgw_get_fields(dgw_ctx *ctx, int shot, double *q);
  * step * dt for the source and the trace index), after dgw_set_fields has
  * loaded the state saved at that step.  The shot's traces before `step` stay
  * as dgw_set_fields left them (zero); the next dgw_step records from `step`
- * on.  Memory variables of a perfectly matched layer are not part of the
- * saved state: they restart at zero.  DGW_ERANGE for a shot out of range, a
+ * on.  Memory variables of a perfectly matched layer restart at zero with
+ * dgw_set_fields; dgw_set_pml_memory restores them.  DGW_ERANGE for a shot out of range, a
  * negative step, or a step beyond the shot's length. */
 int dgw_set_shot_step(dgw_ctx *ctx, int shot, int64_t step);
 
@@ -324,6 +324,13 @@ int dgw_set_pml(dgw_ctx *ctx, int64_t n, const int32_t *elements, const double *
 /* The layer's memory variables of one shot, out [n][18][Np] FP64 (phi_cb at
  * 3 c + b, psi_cb at 9 + 3 c + b).  DGW_ESTATE without a layer. */
 int dgw_get_pml_memory(dgw_ctx *ctx, int shot, double *out);
+
+/* Restore a shot's memory variables (the layout of dgw_get_pml_memory, FP64,
+ * copied; rounded to FP32 in the FP32 form): with dgw_set_fields and
+ * dgw_set_shot_step, a run with a layer resumes exactly where it was saved.
+ * Call it after dgw_set_fields, which restarts them at zero.  DGW_ESTATE
+ * without a layer, DGW_EINVAL for non-finite values. */
+int dgw_set_pml_memory(dgw_ctx *ctx, int shot, const double *in);
 
 /* Average duration of the layer kernel launches of the last timed dgw_step
  * (dgw_enable_timing), and how many were timed. */

@@ -57,6 +57,7 @@ SIGNATURES = {
     "dgw_set_damping": (C.c_int, [_P, _D]),
     "dgw_set_pml": (C.c_int, [_P, _I64, C.POINTER(C.c_int32), _D]),
     "dgw_get_pml_memory": (C.c_int, [_P, C.c_int, _D]),
+    "dgw_set_pml_memory": (C.c_int, [_P, C.c_int, _D]),
     "dgw_pml_kernel_ms": (C.c_int, [_P, _D, _PI64]),
     "dgw_set_stiffness": (C.c_int, [_P, _D]),
     "dgw_set_adjoint_memory": (C.c_int, [_P, _I64]),

@@ -1177,6 +1177,21 @@ int dgw_get_pml_memory(dgw_ctx *c, int shot, double *out) {
   return DGW_OK;
 }
 
+int dgw_set_pml_memory(dgw_ctx *c, int shot, const double *in) {
+  if (!c) return DGW_EINVAL;
+  if (c->pml_n == 0) return c->fail(DGW_ESTATE, "no perfectly matched layer is set");
+  if (shot < 0 || shot >= c->nshots) return c->fail(DGW_ERANGE, "shot out of range");
+  if (!in) return c->fail(DGW_EINVAL, "null input");
+  const size_t n = (size_t)c->pml_n * 18 * c->R.Np;
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(in[i])) return c->fail(DGW_EINVAL, "non-finite memory variable");
+  c->touch();
+  if (c->precision == 64)
+    return c->upload((double *)c->d_pml_mem + shot * n, in, sizeof(double) * n);
+  std::vector<float> tmp(in, in + n);
+  return c->upload((float *)c->d_pml_mem + shot * n, tmp.data(), sizeof(float) * n);
+}
+
 int dgw_pml_kernel_ms(dgw_ctx *c, double *ms, int64_t *launches) {
   if (!c || !ms || !launches) return DGW_EINVAL;
   *ms = c->pml_ms;

@@ -384,6 +384,14 @@ class Solver:
                     "dgw_get_pml_memory")
         return out
 
+    def set_pml_memory(self, shot, m):
+        """Restore a shot's memory variables, [n, 18, Np] (after set_fields)."""
+        a = np.ascontiguousarray(m, dtype=np.float64)
+        if a.shape != (self.pml_n, 18, self.Np):
+            raise ValueError("memory variables must be [n, 18, Np]")
+        self._check(self.lib.dgw_set_pml_memory(self._ctx, int(shot), _dptr(a)),
+                    "dgw_set_pml_memory")
+
     def pml_kernel_ms(self):
         ms = C.c_double()
         n = C.c_int64()

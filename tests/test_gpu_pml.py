@@ -253,6 +253,48 @@ def test_set_fields_restarts_the_memory_variables():
     s.close()
 
 
+def test_resume_with_the_layer():
+    """Saved at step 8 (fields, memory variables, step) and resumed on a new
+    context, a run with the layer equals the uninterrupted run bitwise."""
+    mesh = W.kuhn_cube(3, 1.0)
+    K = mesh["etov"].shape[0]
+    N = 3
+    elems, prof, _, _ = _unit_layer(mesh, N)
+    rho, lam, mu = _random_medium(K, 44)
+    P = oracle_problem(mesh, N)
+    dt = P.suggest_dt(rho, lam, mu, 0.5)
+    src = np.array([0.45, 0.5, 0.55])
+    say("case pml resume")
+
+    def make():
+        s = gpu_solver(mesh, N, rho, lam, mu, dt, kernel=1)
+        s.set_pml(elems, prof)
+        s.set_source(0, src, 6.0, 0.05, 1.0, nsteps=20)
+        s.zero_fields()
+        return s
+
+    a = make()
+    a.step(20)
+    b = make()
+    b.step(8)
+    q8, m8 = b.get_fields(0), b.pml_memory(0)
+    b.close()
+    c = make()
+    c.set_fields(0, q8)
+    c.set_pml_memory(0, m8)
+    c.set_shot_step(0, 8)
+    c.step(12)
+    assert np.array_equal(c.get_fields(0), a.get_fields(0))
+    assert np.array_equal(c.pml_memory(0), a.pml_memory(0))
+    bad = m8.copy()
+    bad[0, 0, 0] = np.nan
+    with pytest.raises(DGWError) as e:
+        c.set_pml_memory(0, bad)
+    assert e.value.code == -1
+    a.close()
+    c.close()
+
+
 def test_pml_arguments_checked():
     mesh = W.kuhn_cube(2, 1.0)
     K = mesh["etov"].shape[0]
