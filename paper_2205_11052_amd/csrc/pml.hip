@@ -34,7 +34,10 @@ using stagec::Sz;
 
 namespace {
 
-constexpr int kPmlThreads = 256;
+// 512 threads: 7 layer elements per work-group at order 4 (two 512-thread
+// work-groups per CU at 128 VGPRs); 0.77 ms per launch on the order-4 FP64
+// benchmark layer against 0.87 ms with 256 threads (3 elements)
+constexpr int kPmlThreads = 512;
 
 template <int N>
 struct PmlSz {
