@@ -685,6 +685,9 @@ def main():
                     help="launch shape 'kernel,elements,wgs_per_cu' (skips the autotuner)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--fp32-probe", action="store_true",
+                    help="only time the FP32 form on the headline workload "
+                         "(counter runs; with --shape)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU "
@@ -706,6 +709,17 @@ def main():
     Np = (N + 1) * (N + 2) * (N + 3) // 6
     dof = 9 * Np * K
 
+    if args.fp32_probe:
+        with torch.cuda.stream(stream):
+            s = build_solver(w, 32, stream=stream.cuda_stream, shape=shape)
+            sec, _ = timed_steps(torch, s, stream, args.steps, args.warmup)
+            kms, nl = kernel_avg_ms(s)
+            shp = s.shape
+            s.close()
+        print(json.dumps({"probe": "fp32", "ms_per_step": round(sec / args.steps * 1e3, 4),
+                          "kernel_avg_ms": round(kms, 5), "launches_timed": nl,
+                          "launch_shape": list(shp)}))
+        return
     with torch.cuda.stream(stream):
         progress("headline: building and autotuning")
         s = build_solver(w, 64, stream=stream.cuda_stream, shape=shape)
