@@ -109,6 +109,7 @@ void fill_adj(dgw_ctx *c, AdjArgs<real> &a, const void *q, void *lq, void *lr,
   a.sponge = c->have_sponge ? c->d_sponge : nullptr;
   a.K = c->mesh.K;
   a.shot_stride = c->mesh.K * 9 * c->R.Np;
+  a.shot_map = nullptr;
   a.shot_step = c->adj->d_aux;
   a.shot_len = c->d_len;
   a.rk_a = rk_a()[stage];
@@ -117,16 +118,21 @@ void fill_adj(dgw_ctx *c, AdjArgs<real> &a, const void *q, void *lq, void *lr,
 }
 
 
-int stage_explicit(dgw_ctx *c, const void *in, void *out, void *res, int stage) {
+// One forward stage of the recomputation over the first `slots` shots of
+// `map` (the shots still active at this step).
+int stage_explicit(dgw_ctx *c, const void *in, void *out, void *res, int stage,
+                   const int32_t *map, int slots) {
   hipError_t e;
   if (c->precision == 64) {
     StageArgs<double> a;
     stage_args(c, a, in, out, res, c->adj->d_aux, stage);
-    e = launch_stage(c->kernel, c->R.N, 64, c->block, c->wpc, c->ncu, c->nshots, &a, c->stream);
+    a.shot_map = map;
+    e = launch_stage(c->kernel, c->R.N, 64, c->block, c->wpc, c->ncu, slots, &a, c->stream);
   } else {
     StageArgs<float> a;
     stage_args(c, a, in, out, res, c->adj->d_aux, stage);
-    e = launch_stage(c->kernel, c->R.N, 32, c->block, c->wpc, c->ncu, c->nshots, &a, c->stream);
+    a.shot_map = map;
+    e = launch_stage(c->kernel, c->R.N, 32, c->block, c->wpc, c->ncu, slots, &a, c->stream);
   }
   if (e != hipSuccess) return c->hipfail(e, "stage kernel launch (recompute)");
   return DGW_OK;
@@ -286,7 +292,20 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
     for (int i = 1; i < 5; ++i) st[i] = alloc(n);
   std::vector<void *> seg;
   for (int64_t i = 0; i < a->every * per_step; ++i) seg.push_back(alloc(n));
-  bool ok = lq && lr && res && zbuf && zbuf2 && grad;
+  // the shots by decreasing length: at reverse step s the active shots (those
+  // longer than s) are a prefix of this order, so every launch covers just
+  // the first nact(s) slots of one map
+  std::vector<int32_t> order(c->nshots);
+  for (int i = 0; i < c->nshots; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return c->h_len[x] > c->h_len[y]; });
+  int32_t *d_order = (int32_t *)alloc(sizeof(int32_t) * c->nshots);
+  auto nact = [&](int64_t s) {
+    int n_ = 0;
+    while (n_ < c->nshots && c->h_len[order[n_]] > s) ++n_;
+    return n_;
+  };
+  bool ok = lq && lr && res && zbuf && zbuf2 && grad && d_order;
   if (!keep) ok = ok && st[1] && st[2] && st[3] && st[4];
   for (void *p : seg) ok = ok && p;
   if (!ok) {
@@ -294,6 +313,10 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
     return c->fail(DGW_ENOMEM, "device allocation failed (adjoint work space)");
   }
   hipError_t e;
+  if ((rc = c->upload(d_order, order.data(), sizeof(int32_t) * c->nshots))) {
+    release();
+    return rc;
+  }
   if ((e = hipMemsetAsync(lq, 0, n, c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(lr, 0, n, c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(res, 0, n, c->stream)) != hipSuccess ||
@@ -327,10 +350,11 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
         break;
       }
       const void *in = seg[idx(s - c0, 0)];
+      const int na = nact(s);
       for (int i = 0; i < (last ? 4 : 5) && rc == DGW_OK; ++i) {
         void *out = i == 4 ? seg[idx(s - c0 + 1, 0)]
                            : keep ? seg[idx(s - c0, i + 1)] : st[1 + (i & 1)];
-        rc = stage_explicit(c, in, out, res, i);
+        if (na > 0) rc = stage_explicit(c, in, out, res, i, d_order, na);
         in = out;
       }
     }
@@ -353,23 +377,26 @@ int dgw_adjoint(dgw_ctx *c, double *g_rho, double *g_lam, double *g_mu) {
         sx[0] = seg[idx(s - c0, 0)];
         for (int i = 1; i < 5; ++i) sx[i] = st[i];
         for (int i = 0; i < 4 && rc == DGW_OK; ++i)
-          rc = stage_explicit(c, sx[i], sx[i + 1], res, i);
+          rc = stage_explicit(c, sx[i], sx[i + 1], res, i, d_order, nact(s));
       }
       // the step's first reverse stage lifts w itself (after the
       // injection); each later one reads what the previous main kernel
       // formed, the two buffers alternating
       void *zc = zbuf, *zx = zbuf2;
-      for (int i = 4; i >= 0 && rc == DGW_OK; --i) {
+      const int na = nact(s);
+      for (int i = 4; i >= 0 && rc == DGW_OK && na > 0; --i) {
         const bool tm = c->timing && timed_used + 2 <= (int)c->adj_ev.size();
         if (tm) (void)hipEventRecord(c->adj_ev[timed_used], c->stream);
         if (c->precision == 64) {
           AdjArgs<double> aa;
           fill_adj(c, aa, sx[i], lq, lr, zc, zx, grad, i);
-          e = launch_adjoint_stage(c->R.N, 64, c->nshots, &aa, i == 4, c->stream);
+          aa.shot_map = d_order;
+          e = launch_adjoint_stage(c->R.N, 64, na, &aa, i == 4, c->stream);
         } else {
           AdjArgs<float> aa;
           fill_adj(c, aa, sx[i], lq, lr, zc, zx, grad, i);
-          e = launch_adjoint_stage(c->R.N, 32, c->nshots, &aa, i == 4, c->stream);
+          aa.shot_map = d_order;
+          e = launch_adjoint_stage(c->R.N, 32, na, &aa, i == 4, c->stream);
         }
         std::swap(zc, zx);
         if (e != hipSuccess) rc = c->hipfail(e, "adjoint stage launch");

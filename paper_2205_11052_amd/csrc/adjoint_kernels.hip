@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kT) adj_lift_kernel(AdjArgs<real> A) {
   __shared__ real sw[BE * 9 * Np];
   __shared__ double sfs[BE * 4];
   __shared__ double sgeo[BE * 13];   // 1/rho and the four outward normals
-  const int shot = blockIdx.y;
+  const int shot = A.shot_map ? A.shot_map[blockIdx.y] : (int)blockIdx.y;
   const int64_t k0 = (int64_t)blockIdx.x * BE;
   if (k0 >= A.K) return;   // never taken (the grid covers the mesh exactly)
   const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
   __shared__ double sgv[BE * 3 * Np];
   __shared__ double smeta[BE * DGW_META];
 
-  const int shot = blockIdx.y;
+  const int shot = A.shot_map ? A.shot_map[blockIdx.y] : (int)blockIdx.y;
   const int64_t k0 = (int64_t)blockIdx.x * BE;
   if (k0 >= A.K) return;   // never taken (the grid covers the mesh exactly)
   const int nE = (int)((A.K - k0) < BE ? (A.K - k0) : BE);

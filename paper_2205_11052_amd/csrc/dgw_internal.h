@@ -202,12 +202,13 @@ struct AdjArgs {
   const double *sponge;         // [K] damping rate, or null
   int64_t K;
   int64_t shot_stride;
+  const int32_t *shot_map;      // shot of each launched slot, or null (as in StageArgs)
   const int64_t *shot_step;
   const int64_t *shot_len;
   double rk_a, rk_b, dt;
 };
 
-// Launchers (adjoint_kernels.hip).
+// Launchers (adjoint_kernels.hip); nshots is the number of launched slots.
 // lift: launch the lift kernel first (else zbuf already holds the stage's
 // lifted adjoint, formed by the previous stage's main kernel)
 hipError_t launch_adjoint_stage(int N, int precision, int nshots,
