@@ -35,8 +35,8 @@ using stagec::Sz;
 namespace {
 
 // 512 threads: 7 layer elements per work-group at order 4 (two 512-thread
-// work-groups per CU at 128 VGPRs); 0.77 ms per launch on the order-4 FP64
-// benchmark layer against 0.87 ms with 256 threads (3 elements)
+// work-groups per CU at 110 VGPRs); 0.48 ms per launch on the order-4 FP64
+// benchmark layer against 0.52 ms with 256 threads (3 elements)
 constexpr int kPmlThreads = 512;
 
 template <int N>
@@ -50,6 +50,9 @@ template <int N, typename real>
 __global__ void __launch_bounds__(kPmlThreads) pml_kernel(PmlArgs<real> A) {
   constexpr int Np = Sz<N>::Np, Nfp = Sz<N>::Nfp, NF = 4 * Nfp;
   constexpr int PB = PmlSz<N>::PB;
+  // per-thread counts of the block's field and per-element loads
+  constexpr int NQ = (PB * 9 * Np + kPmlThreads - 1) / kPmlThreads;
+  constexpr int NM = (PB * DGW_META + kPmlThreads - 1) / kPmlThreads;
   __shared__ real sq[PB * 9 * Np];
   __shared__ real sfl[PB * NF * 6];
   __shared__ double smeta[PB * DGW_META];
@@ -66,15 +69,39 @@ __global__ void __launch_bounds__(kPmlThreads) pml_kernel(PmlArgs<real> A) {
   real *__restrict__ mres = A.mres + shot * A.mem_stride;
   const int tid = threadIdx.x;
 
+  // The global loads of each phase are unconditional (clamped in-bounds
+  // indices, results selected afterwards) and issued before any is waited
+  // for: a load under a branch, or one whose use follows it at once, makes
+  // the wave wait out a full memory round trip per load.
   if (tid < nE) sk[tid] = A.elem[p0 + tid];
   __syncthreads();
-  for (int t = tid; t < nE * 9 * Np; t += kPmlThreads) {
-    const int e = t / (9 * Np), r = t - e * 9 * Np;
-    sq[t] = qin[sk[e] * 9 * Np + r];
-  }
-  for (int t = tid; t < nE * DGW_META; t += kPmlThreads) {
-    const int e = t / DGW_META, r = t - e * DGW_META;
-    smeta[t] = A.meta[sk[e] * DGW_META + r];
+  {
+    real vq[NQ];
+    double vm[NM];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      const int t = tid + j * kPmlThreads;
+      const int tc = t < nE * 9 * Np ? t : 0;
+      const int e = tc / (9 * Np), r = tc - e * 9 * Np;
+      vq[j] = qin[sk[e] * 9 * Np + r];
+    }
+#pragma unroll
+    for (int j = 0; j < NM; ++j) {
+      const int t = tid + j * kPmlThreads;
+      const int tc = t < nE * DGW_META ? t : 0;
+      const int e = tc / DGW_META, r = tc - e * DGW_META;
+      vm[j] = A.meta[sk[e] * DGW_META + r];
+    }
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      const int t = tid + j * kPmlThreads;
+      if (t < nE * 9 * Np) sq[t] = vq[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NM; ++j) {
+      const int t = tid + j * kPmlThreads;
+      if (t < nE * DGW_META) smeta[t] = vm[j];
+    }
   }
   __syncthreads();
 
@@ -85,24 +112,21 @@ __global__ void __launch_bounds__(kPmlThreads) pml_kernel(PmlArgs<real> A) {
     const double *g = smeta + e * DGW_META;
     const real *qe = sq + e * 9 * Np;
     const int n1 = A.fmask[fm];
-    real qm[9], p[9];
+    const int cn = A.conn[k * 4 + f];
+    const int nn = A.nbnode[k * NF + fm];
+    // the neighbour's trace, read from the element itself on boundary faces
+    const int64_t nb = cn >= 0 ? (int64_t)(cn >> 5) : k;
+    const int nc = cn >= 0 ? nn : 0;
+    real pn[9], qm[9], p[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) pn[c] = qin[(nb * 9 + c) * Np + nc];
 #pragma unroll
     for (int c = 0; c < 9; ++c) qm[c] = qe[c * Np + n1];
-    const int cn = A.conn[k * 4 + f];
-    if (cn >= 0) {
-      const int64_t nb = (int64_t)(cn >> 5);
-      const int nn = A.nbnode[k * NF + fm];
+    // interior: the neighbour's trace; free surface: the mirror state (v, -sigma);
+    // absorbing: the zero state
 #pragma unroll
-      for (int c = 0; c < 9; ++c) p[c] = qin[(nb * 9 + c) * Np + nn];
-    } else if (cn == CONN_FREE) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) p[c] = qm[c];
-#pragma unroll
-      for (int c = 3; c < 9; ++c) p[c] = -qm[c];
-    } else {
-#pragma unroll
-      for (int c = 0; c < 9; ++c) p[c] = (real)0;
-    }
+    for (int c = 0; c < 9; ++c)
+      p[c] = cn >= 0 ? pn[c] : cn == CONN_FREE ? (c < 3 ? qm[c] : -qm[c]) : (real)0;
     const real nx = (real)g[M_NORMAL + 3 * f], ny = (real)g[M_NORMAL + 3 * f + 1],
                nz = (real)g[M_NORMAL + 3 * f + 2];
     const real dvx = p[0] - qm[0], dvy = p[1] - qm[1], dvz = p[2] - qm[2];
@@ -153,8 +177,12 @@ __global__ void __launch_bounds__(kPmlThreads) pml_kernel(PmlArgs<real> A) {
   int oz;
   asm volatile("v_mov_b32 %0, 0" : "=v"(oz));
   constexpr int UJ = Np % 7 == 0 ? 7 : Np % 5 == 0 ? 5 : 4;   // divides Np
-  // reference derivatives of the role's fields: velocity (3) or stress (6)
+  // reference derivatives of six fields from c0: the velocity role needs
+  // the first three (its other three sums are not used), the stress role
+  // all six; the same loop for both keeps it free of branches, so each
+  // chunk's operator loads are issued together
   const int c0 = vel ? 0 : 3;
+  const real *qc = qe + c0 * Np;
   real acc[6][3];
 #pragma unroll
   for (int c = 0; c < 6; ++c) acc[c][0] = acc[c][1] = acc[c][2] = (real)0;
@@ -162,16 +190,21 @@ __global__ void __launch_bounds__(kPmlThreads) pml_kernel(PmlArgs<real> A) {
     const real *pr = A.DrT + i + oz, *ps = A.DsT + i + oz, *pt = A.DtT + i + oz;
 #pragma unroll 1
     for (int j0 = 0; j0 < Np; j0 += UJ) {
+      real a0[UJ], a1[UJ], a2[UJ];
 #pragma unroll
       for (int w = 0; w < UJ; ++w) {
-        const real a0 = pr[w * Np], a1 = ps[w * Np], a2 = pt[w * Np];
+        a0[w] = pr[w * Np];
+        a1[w] = ps[w * Np];
+        a2[w] = pt[w * Np];
+      }
+#pragma unroll
+      for (int w = 0; w < UJ; ++w) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-          if (vel && c >= 3) continue;
-          const real v = qe[(c0 + c) * Np + j0 + w];
-          acc[c][0] += a0 * v;
-          acc[c][1] += a1 * v;
-          acc[c][2] += a2 * v;
+          const real v = qc[c * Np + j0 + w];
+          acc[c][0] += a0[w] * v;
+          acc[c][1] += a1[w] * v;
+          acc[c][2] += a2[w] * v;
         }
       }
       pr += UJ * Np;
@@ -189,8 +222,10 @@ __global__ void __launch_bounds__(kPmlThreads) pml_kernel(PmlArgs<real> A) {
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const int s = vel ? c : vo[c][b];
-      Dg[c][b] = X[b] * acc[s][0] + X[3 + b] * acc[s][1] + X[6 + b] * acc[s][2];
+      const real s0 = vel ? acc[c][0] : acc[vo[c][b]][0];
+      const real s1 = vel ? acc[c][1] : acc[vo[c][b]][1];
+      const real s2 = vel ? acc[c][2] : acc[vo[c][b]][2];
+      Dg[c][b] = X[b] * s0 + X[3 + b] * s1 + X[6 + b] * s2;
     }
   // face part: the lifted traction change W (stress role) or velocity
   // change U (velocity role) of each face, with the face's normal
@@ -199,82 +234,90 @@ __global__ void __launch_bounds__(kPmlThreads) pml_kernel(PmlArgs<real> A) {
     const real *pl = A.LIFTT + i + oz;
 #pragma unroll 1
     for (int f = 0; f < 4; ++f) {
+      real l[Nfp];
+#pragma unroll
+      for (int m = 0; m < Nfp; ++m) l[m] = pl[(f * Nfp + m) * Np];
       real W0 = 0, W1 = 0, W2 = 0;
 #pragma unroll
       for (int m = 0; m < Nfp; ++m) {
-        const real l = pl[(f * Nfp + m) * Np];
         const real *s3 = fle + (f * Nfp + m) * 6;
-        W0 += l * s3[0];
-        W1 += l * s3[1];
-        W2 += l * s3[2];
+        W0 += l[m] * s3[0];
+        W1 += l[m] * s3[1];
+        W2 += l[m] * s3[2];
       }
       const real n[3] = {(real)g[M_NORMAL + 3 * f], (real)g[M_NORMAL + 3 * f + 1],
                          (real)g[M_NORMAL + 3 * f + 2]};
       const real Wv[3] = {W0, W1, W2};
-      if (vel) {
+      // velocity role: n_b U_c; stress role: n is constant on the face, so
+      // the lift of n_b S_cb is n_b (W_c n_b + n_c W_b - n_c n_b (n.W))
+      const real nW = n[0] * W0 + n[1] * W1 + n[2] * W2;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int b = 0; b < 3; ++b) Dg[c][b] += n[b] * Wv[c];
-      } else {
-        // n is constant on the face, so the lift of n_b S_cb is
-        // n_b (W_c n_b + n_c W_b - n_c n_b (n.W))
-        const real nW = n[0] * W0 + n[1] * W1 + n[2] * W2;
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int b = 0; b < 3; ++b)
-            Dg[c][b] += n[b] * (Wv[c] * n[b] + n[c] * Wv[b] - n[c] * n[b] * nW);
-      }
+        for (int b = 0; b < 3; ++b)
+          Dg[c][b] += vel ? n[b] * Wv[c]
+                          : n[b] * (Wv[c] * n[b] + n[c] * Wv[b] - n[c] * n[b] * nW);
     }
   }
-  // the role's nine memory variables (phi for the stress role, psi for the
-  // velocity role) at the stage input, and the node's profile
+  // every remaining load at once: the role's nine memory variables (phi for
+  // the stress role, psi for the velocity role) and their residuals, the
+  // node's profile, and the residual and output entries the role updates
+  // (stress components for the velocity role, velocity for the stress
+  // role; the stress role's last three slots repeat its first)
   const int64_t mb = pi * 18 * Np + (vel ? 9 * Np : 0) + i;
-  real mv[9];
+  const int nout = vel ? 6 : 3, fb = vel ? 3 : 0;
+  real mv[9], mr[9], db[3], ab[3], rv[6], ov[6];
 #pragma unroll
   for (int w = 0; w < 9; ++w) mv[w] = mem[mb + w * Np];
-  real db[3], ab[3];
+#pragma unroll
+  for (int w = 0; w < 9; ++w) mr[w] = mres[mb + w * Np];
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
     db[b] = (real)A.prof[(pi * 6 + b) * Np + i];
     ab[b] = (real)A.prof[(pi * 6 + 3 + b) * Np + i];
   }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const int64_t idx = (k * 9 + fb + (c < nout ? c : 0)) * Np + i;
+    rv[c] = res[idx];
+    ov[c] = qout[idx];
+  }
   const real ra = (real)A.rk_a, rb = (real)A.rk_b, rdt = (real)A.dt;
-  // the layer's terms: (1/rho) sum_b phi_cb on v_c, or
-  // lambda tr(Psi) I + mu (Psi + Psi^T) on sigma
-  if (vel) {
-    const real la = (real)g[M_LAM], mu = (real)g[M_MU];
+  // the layer's terms: lambda tr(Psi) I + mu (Psi + Psi^T) on sigma
+  // (velocity role), or (1/rho) sum_b phi_cb on v_c (stress role)
+  real dl[6];
+  {
+    const real la = (real)g[M_LAM], mu = (real)g[M_MU], ri = (real)g[M_RHOINV];
     const real tr = mv[0] + mv[4] + mv[8];
-    const real dl[6] = {la * tr + 2 * mu * mv[0], la * tr + 2 * mu * mv[4],
+    const real ds[6] = {la * tr + 2 * mu * mv[0], la * tr + 2 * mu * mv[4],
                         la * tr + 2 * mu * mv[8], mu * (mv[5] + mv[7]),
                         mu * (mv[2] + mv[6]), mu * (mv[1] + mv[3])};
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      const int64_t idx = (k * 9 + 3 + c) * Np + i;
-      const real add = rdt * dl[c];
-      res[idx] = res[idx] + add;
-      qout[idx] = qout[idx] + rb * add;
-    }
-  } else {
-    const real ri = (real)g[M_RHOINV];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int64_t idx = (k * 9 + c) * Np + i;
-      const real add = rdt * (ri * (mv[3 * c] + mv[3 * c + 1] + mv[3 * c + 2]));
-      res[idx] = res[idx] + add;
-      qout[idx] = qout[idx] + rb * add;
+      const int cv = c < 3 ? c : 0;
+      const real dv = ri * (mv[3 * cv] + mv[3 * cv + 1] + mv[3 * cv + 2]);
+      dl[c] = vel ? ds[c] : dv;
     }
   }
-  // memory update: m_t = -(d_b + alpha_b) m_cb - d_b (D or G)_cb
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    if (c < nout) {
+      const int64_t idx = (k * 9 + fb + c) * Np + i;
+      const real add = rdt * dl[c];
+      res[idx] = rv[c] + add;
+      qout[idx] = ov[c] + rb * add;
+    }
+  }
+  // memory update: m_t = -(d_b + alpha_b) m_cb - d_b (D or G)_cb; stage 1
+  // (a = 0) takes no part of mres, so stale values cannot leak in
+  const bool first = A.rk_a == 0.0;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       const int w = 3 * c + b;
       const real rate = -(db[b] + ab[b]) * mv[w] - db[b] * Dg[c][b];
-      // stage 1 (a = 0) never reads mres, so stale values cannot leak in
-      const real r = (A.rk_a == 0.0) ? rdt * rate : ra * mres[mb + w * Np] + rdt * rate;
+      const real r = first ? rdt * rate : ra * mr[w] + rdt * rate;
       mres[mb + w * Np] = r;
       mem[mb + w * Np] = mv[w] + rb * r;
     }
