@@ -471,6 +471,16 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
     const real ri = (real)g[M_RHOINV], la = (real)g[M_LAM], mu = (real)g[M_MU];
     const real *we = sw + e * 9 * Np;
     const real *qe = sq + e * 9 * Np;
+    // this node's lam_q entries and face positions, issued here so that
+    // their latency overlaps the derivative loop (loaded one by one where
+    // they are used, each would cost a full memory round trip: lam_q is
+    // written back between them)
+    real lqv[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) lqv[c] = lq[(k * 9 + c) * Np + i];
+    int mmv[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) mmv[f] = A.facepos[f * Np + i];
     // D_r^T w, D_s^T w, D_t^T w of the nine fields at node i: column i of
     // D_a^T is row i of D_a, stored [j][i] = D(j, i), walked in chunks of
     // immediate offsets
@@ -552,7 +562,7 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
     const real *fa = sfa + e * 9 * NF;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      const int mm = A.facepos[f * Np + i];
+      const int mm = mmv[f];
       if (mm >= 0) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) adj[c] += fa[c * NF + f * Nfp + mm];
@@ -563,7 +573,7 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       const int64_t idx = (k * 9 + c) * Np + i;
-      const real lqn = lq[idx] + rdt * adj[c];
+      const real lqn = lqv[c] + rdt * adj[c];
       const real lrn = ra * we[c * Np + i];
       lq[idx] = lqn;
       lr[idx] = lrn;
@@ -583,6 +593,8 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
       real acc[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[c] = 0;
+      // fully unrolled: every LIFT entry is loaded before the first is used
+#pragma unroll
       for (int i = 0; i < Np; ++i) {
         const real l = A.LIFT[i * NF + fm];
 #pragma unroll
