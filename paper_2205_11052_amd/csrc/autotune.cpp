@@ -112,35 +112,40 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *kernel,
   Shape best = opts[0];
   float best_ms = 1e30f;
   int rc = DGW_OK;
-  for (const auto &o : opts) {
-    hipError_t err = hipSuccess;
-    const int reps = 10;
-    for (int r = 0; r < reps + 2 && err == hipSuccess; ++r) {
-      if (r == 2) (void)hipEventRecord(e0, c->stream);
-      if (c->precision == 64) {
-        StageArgs<double> a;
-        stage_args(c, a, c->d_q[c->cur], out, res, c->d_step, 1);
-        err = launch_stage(o.kernel, c->R.N, 64, o.be, o.wpc, c->ncu, c->nshots, &a,
-                           c->stream);
-      } else {
-        StageArgs<float> a;
-        stage_args(c, a, c->d_q[c->cur], out, res, c->d_step, 1);
-        err = launch_stage(o.kernel, c->R.N, 32, o.be, o.wpc, c->ncu, c->nshots, &a,
-                           c->stream);
+  // two passes over the candidates, each shape's best time counting: the
+  // first shapes of a single pass ran while the clocks were still rising
+  // and read up to 7% slow
+  for (int pass = 0; pass < 2 && rc == DGW_OK; ++pass) {
+    for (const auto &o : opts) {
+      hipError_t err = hipSuccess;
+      const int reps = 10;
+      for (int r = 0; r < reps + 2 && err == hipSuccess; ++r) {
+        if (r == 2) (void)hipEventRecord(e0, c->stream);
+        if (c->precision == 64) {
+          StageArgs<double> a;
+          stage_args(c, a, c->d_q[c->cur], out, res, c->d_step, 1);
+          err = launch_stage(o.kernel, c->R.N, 64, o.be, o.wpc, c->ncu, c->nshots, &a,
+                             c->stream);
+        } else {
+          StageArgs<float> a;
+          stage_args(c, a, c->d_q[c->cur], out, res, c->d_step, 1);
+          err = launch_stage(o.kernel, c->R.N, 32, o.be, o.wpc, c->ncu, c->nshots, &a,
+                             c->stream);
+        }
       }
-    }
-    if (err != hipSuccess) {
-      rc = c->hipfail(err, "autotune launch");
-      break;
-    }
-    (void)hipEventRecord(e1, c->stream);
-    (void)hipEventSynchronize(e1);
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    ms /= reps;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = o;
+      if (err != hipSuccess) {
+        rc = c->hipfail(err, "autotune launch");
+        break;
+      }
+      (void)hipEventRecord(e1, c->stream);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms /= reps;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = o;
+      }
     }
   }
   (void)hipStreamSynchronize(c->stream);

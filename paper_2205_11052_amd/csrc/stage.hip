@@ -437,16 +437,24 @@ __device__ __forceinline__ void phase3_nodes(const StageArgs<real> &A, const rea
 #pragma unroll 1   // unrolled, the persistent form hoists too much and spills
     for (int f = 0; f < 4; ++f) {
       real U0 = 0, U1 = 0, U2 = 0;
+      // the face's lift entries in chunks of LC, each chunk's loads issued
+      // before its first use (one by one, every entry cost a round trip)
+      constexpr int LC = Nfp % 7 == 0 ? 7 : Nfp % 5 == 0 ? 5 : Nfp;
 #pragma unroll
-      for (int m = 0; m < Nfp; ++m) {
-        const real l = pl[(f * Nfp + m) * Np];
-        const real *s6 = fle + (f * Nfp + m) * 6;
-        V0 += l * s6[0];
-        V1 += l * s6[1];
-        V2 += l * s6[2];
-        U0 += l * s6[3];
-        U1 += l * s6[4];
-        U2 += l * s6[5];
+      for (int m0 = 0; m0 < Nfp; m0 += LC) {
+        real l[LC];
+#pragma unroll
+        for (int u = 0; u < LC; ++u) l[u] = pl[(f * Nfp + m0 + u) * Np];
+#pragma unroll
+        for (int u = 0; u < LC; ++u) {
+          const real *s6 = fle + (f * Nfp + m0 + u) * 6;
+          V0 += l[u] * s6[0];
+          V1 += l[u] * s6[1];
+          V2 += l[u] * s6[2];
+          U0 += l[u] * s6[3];
+          U1 += l[u] * s6[4];
+          U2 += l[u] * s6[5];
+        }
       }
       const real nx = (real)g[M_NORMAL + 3 * f], ny = (real)g[M_NORMAL + 3 * f + 1],
                  nz = (real)g[M_NORMAL + 3 * f + 2];
