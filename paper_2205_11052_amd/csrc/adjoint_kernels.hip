@@ -491,15 +491,31 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
       const real *pr = A.Dr + i, *ps = A.Ds + i, *pt = A.Dt + i;
 #pragma unroll 1
       for (int j0 = 0; j0 < Np; j0 += UJ) {
+        // FP32: the chunk's operator entries are loaded together (the
+        // registers are there); FP64 keeps the compiler's one-step lead,
+        // whose registers keep three waves per SIMD
+        real a0[UJ], a1[UJ], a2[UJ];
+        if constexpr (sizeof(real) == 4) {
+#pragma unroll
+          for (int u = 0; u < UJ; ++u) {
+            a0[u] = pr[u * Np];
+            a1[u] = ps[u * Np];
+            a2[u] = pt[u * Np];
+          }
+        }
 #pragma unroll
         for (int u = 0; u < UJ; ++u) {
-          const real a0 = pr[u * Np], a1 = ps[u * Np], a2 = pt[u * Np];
+          if constexpr (sizeof(real) != 4) {
+            a0[u] = pr[u * Np];
+            a1[u] = ps[u * Np];
+            a2[u] = pt[u * Np];
+          }
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
             const real x = we[c * Np + j0 + u];
-            ar[c] += a0 * x;
-            as[c] += a1 * x;
-            at[c] += a2 * x;
+            ar[c] += a0[u] * x;
+            as[c] += a1[u] * x;
+            at[c] += a2[u] * x;
           }
         }
         pr += UJ * Np;
