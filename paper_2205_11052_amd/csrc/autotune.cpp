@@ -121,14 +121,17 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *kernel,
       const int reps = 10;
       for (int r = 0; r < reps + 2 && err == hipSuccess; ++r) {
         if (r == 2) (void)hipEventRecord(e0, c->stream);
+        // every stage index in turn (the first stage reads no residual,
+        // which the node-per-thread form skips), each twice over the reps
+        const int si = r % 5;
         if (c->precision == 64) {
           StageArgs<double> a;
-          stage_args(c, a, c->d_q[c->cur], out, res, c->d_step, 1);
+          stage_args(c, a, c->d_q[c->cur], out, res, c->d_step, si);
           err = launch_stage(o.kernel, c->R.N, 64, o.be, o.wpc, c->ncu, c->nshots, &a,
                              c->stream);
         } else {
           StageArgs<float> a;
-          stage_args(c, a, c->d_q[c->cur], out, res, c->d_step, 1);
+          stage_args(c, a, c->d_q[c->cur], out, res, c->d_step, si);
           err = launch_stage(o.kernel, c->R.N, 32, o.be, o.wpc, c->ncu, c->nshots, &a,
                              c->stream);
         }
