@@ -121,8 +121,8 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *kernel,
       const int reps = 10;
       for (int r = 0; r < reps + 2 && err == hipSuccess; ++r) {
         if (r == 2) (void)hipEventRecord(e0, c->stream);
-        // every stage index in turn (the first stage reads no residual,
-        // which the node-per-thread form skips), each twice over the reps
+        // every stage index in turn (the first stage reads no residual),
+        // each twice over the reps
         const int si = r % 5;
         if (c->precision == 64) {
           StageArgs<double> a;
