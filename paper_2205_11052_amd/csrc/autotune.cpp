@@ -113,8 +113,7 @@ extern "C" int dgw_autotune(dgw_ctx *c, const char *cache_path, int *kernel,
   float best_ms = 1e30f;
   int rc = DGW_OK;
   // two passes over the candidates, each shape's best time counting: the
-  // first shapes of a single pass ran while the clocks were still rising
-  // and read up to 7% slow
+  // first shapes of a single pass run while the clocks are still rising
   for (int pass = 0; pass < 2 && rc == DGW_OK; ++pass) {
     for (const auto &o : opts) {
       hipError_t err = hipSuccess;
