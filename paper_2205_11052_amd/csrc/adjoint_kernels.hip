@@ -471,16 +471,6 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
     const real ri = (real)g[M_RHOINV], la = (real)g[M_LAM], mu = (real)g[M_MU];
     const real *we = sw + e * 9 * Np;
     const real *qe = sq + e * 9 * Np;
-    // this node's lam_q entries and face positions, issued here so that
-    // their latency overlaps the derivative loop (loaded one by one where
-    // they are used, each would cost a full memory round trip: lam_q is
-    // written back between them)
-    real lqv[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) lqv[c] = lq[(k * 9 + c) * Np + i];
-    int mmv[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) mmv[f] = A.facepos[f * Np + i];
     // D_r^T w, D_s^T w, D_t^T w of the nine fields at node i: column i of
     // D_a^T is row i of D_a, stored [j][i] = D(j, i), walked in chunks of
     // immediate offsets
@@ -495,21 +485,14 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
         // registers are there); FP64 keeps the compiler's one-step lead,
         // whose registers keep three waves per SIMD
         real a0[UJ], a1[UJ], a2[UJ];
-        if constexpr (sizeof(real) == 4) {
 #pragma unroll
-          for (int u = 0; u < UJ; ++u) {
-            a0[u] = pr[u * Np];
-            a1[u] = ps[u * Np];
-            a2[u] = pt[u * Np];
-          }
+        for (int u = 0; u < UJ; ++u) {
+          a0[u] = pr[u * Np];
+          a1[u] = ps[u * Np];
+          a2[u] = pt[u * Np];
         }
 #pragma unroll
         for (int u = 0; u < UJ; ++u) {
-          if constexpr (sizeof(real) != 4) {
-            a0[u] = pr[u * Np];
-            a1[u] = ps[u * Np];
-            a2[u] = pt[u * Np];
-          }
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
             const real x = we[c * Np + j0 + u];
@@ -523,6 +506,15 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
         pt += UJ * Np;
       }
     }
+    // this node's lam_q entries and face positions, loaded together (one by
+    // one where they are used, each would cost a full memory round trip:
+    // lam_q is written back between them)
+    real lqv[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) lqv[c] = lq[(k * 9 + c) * Np + i];
+    int mmv[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) mmv[f] = A.facepos[f * Np + i];
     // sum_a X^-1[a][b] (D_a^T w_c) at node i
     auto DTw = [&](int c, int bb) -> real {
       return X[bb] * ar[c] + X[3 + bb] * as[c] + X[6 + bb] * at[c];
