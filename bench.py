@@ -320,6 +320,50 @@ def adjoint_form(torch, stream, nsteps=1500, ckpt=100, n_fd=2):
     return res
 
 
+def adjoint_probe(torch, stream, nsteps=200, ckpt=100):
+    """One gradient of the order-3 gradient workload (24576 tetrahedra) over
+    a short window, FP64 then FP32, for counter runs of the reverse-sweep
+    kernels: observed data from the true layered medium, gradient at the
+    blob-perturbed start, checkpoints every 100 steps."""
+    import workloads as W
+    from paper_2205_11052_amd import Solver
+    wt = W.build_workload("c3_adjoint")
+    ws = W.build_workload("c3_adjoint", medium="blob")
+
+    def make(prec, w, dt=None):
+        s = Solver(w["N"], prec, 1, stream=stream.cuda_stream)
+        s.set_mesh_dict(w["mesh"])
+        s.set_material(w["rho"], w["lam"], w["mu"])
+        s.set_dt(dt if dt is not None else s.suggest_dt(w["cfl"]))
+        s.set_source(0, w["source"], w["f0"], w["t0"], w["amp"])
+        s.set_receivers(0, w["receivers"], nsteps)
+        # the autotuner's picks for this workload, fixed for the counters
+        if prec == 64:
+            s.set_launch(1, 7, 0)
+        else:
+            s.set_launch(0, 12, 0)
+        return s
+
+    out = {"probe": "adjoint", "steps": nsteps, "checkpoint_every": ckpt}
+    with torch.cuda.stream(stream):
+        st = make(64, wt)
+        dt = st.dt
+        st.zero_fields()
+        st.step(nsteps)
+        d = st.read_traces(0)[None]
+        st.close()
+        for prec in (64, 32):
+            s = make(prec, ws, dt)
+            s.zero_fields()
+            mis = s.forward_checkpointed(nsteps, ckpt, d)
+            g = s.adjoint()
+            out["fp%d_misfit" % prec] = float(mis[0])
+            out["fp%d_grad_finite" % prec] = bool(all(np.isfinite(x).all() for x in g))
+            s.close()
+        torch.cuda.synchronize()
+    return out
+
+
 def reverse_stage_bytes(K, Np, real_bytes):
     """Algorithmic HBM bytes of one reverse (adjoint) stage: the stage input
     q read, the adjoint states lam_q and lam_r read and written, the
@@ -688,6 +732,9 @@ def main():
     ap.add_argument("--fp32-probe", action="store_true",
                     help="only time the FP32 form on the headline workload "
                          "(counter runs; with --shape)")
+    ap.add_argument("--adjoint-probe", action="store_true",
+                    help="only one short gradient of the order-3 workload, "
+                         "FP64 then FP32 (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU "
@@ -701,6 +748,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(torch)
+        return
+    if args.adjoint_probe:
+        print(json.dumps(adjoint_probe(torch, torch.cuda.Stream())))
         return
     shape = tuple(int(x) for x in args.shape.split(",")) if args.shape else None
     stream = torch.cuda.Stream()
