@@ -372,6 +372,27 @@ def reverse_stage_bytes(K, Np, real_bytes):
     return K * (5 * 9 * Np * real_bytes + META_BYTES + 2 * 3 * 8)
 
 
+# HBM traffic of one reverse stage of the order-3 gradient workload (the
+# main kernel plus a fifth of a lift, per dispatch, calibrated FETCH_SIZE x
+# 2.0 and WRITE_SIZE x 1.0, from `bench.py --adjoint-probe`), reported only
+# while the reverse-sweep kernel source hashes to the value it was measured
+# for.
+MEASURED_ADJ_TRAFFIC = {
+    "kernel_source_sha256": "9a98fd44e4c1608177744cd8a54f66aa030605e22c3f4576f7748c02e17dd570",
+    "bytes_per_reverse_stage": {64: 365053747 + 132779930 // 5,
+                                32: 188596736 + 70089728 // 5},
+}
+
+
+def adjoint_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("adjoint_kernels.hip", "dgw_internal.h"):
+        with open(os.path.join(ROOT, "paper_2205_11052_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def adjoint_kernel_times(torch, stream, make, ws, dt, d, nsteps=100):
     """Average duration of one reverse stage (its two launches) and of one
     forward stage launch, timed with HIP events on the library's stream in a
@@ -399,6 +420,12 @@ def adjoint_kernel_times(torch, stream, make, ws, dt, d, nsteps=100):
                 "reverse_hbm_frac": round(b / (rms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                 "forward_hbm_frac": round(stage_bytes(K, Np, prec // 8) / (fms / 1e3) / 1e9
                                           / HBM_PEAK_GBS, 4)}
+            m = MEASURED_ADJ_TRAFFIC
+            if m["kernel_source_sha256"] == adjoint_source_sha():
+                t = m["bytes_per_reverse_stage"][prec]
+                out["fp%d" % prec]["reverse_traffic_per_stage"] = t
+                out["fp%d" % prec]["reverse_traffic_hbm_frac"] = round(
+                    t / (rms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     return out
 
 
