@@ -9,21 +9,26 @@
 namespace dgw {
 
 
-template <typename real>
+// Np is a template parameter so that the weight-times-field loop unrolls
+// and each thread issues all of its loads before the first is used (with a
+// run-time Np the loads went out a few at a time: 17 us per launch on the
+// order-4 benchmark workload).  The sum runs over j in order, as before.
+template <typename real, int Np>
 __global__ void __launch_bounds__(256) receiver_kernel(RecArgs A) {
   const int shot = blockIdx.x;
   const int64_t step = A.shot_step[shot];
   if (step >= A.shot_len[shot]) return;
   const real *q = (const real *)A.q + shot * A.shot_stride;
   const int nr = A.nrec[shot];
-  const int Np = A.Np;
   if (step < A.cap) {
     for (int t = threadIdx.x; t < nr * 3; t += blockDim.x) {
       const int r = t / 3, c = t - 3 * r;
       const int64_t k = A.rec_elem[shot * A.rmax + r];
       const double *w = A.rec_w + ((int64_t)shot * A.rmax + r) * Np;
+      const real *qk = q + (k * 9 + c) * Np;
       double s = 0.0;
-      for (int j = 0; j < Np; ++j) s += w[j] * (double)q[(k * 9 + c) * Np + j];
+#pragma unroll
+      for (int j = 0; j < Np; ++j) s += w[j] * (double)qk[j];
       A.trace[(((int64_t)shot * A.rmax + r) * 3 + c) * A.cap + step] = s;
     }
   }
@@ -103,13 +108,24 @@ __global__ void __launch_bounds__(256) finite_kernel(const real *q, int64_t n,
   if (bad) atomicOr(flag, 1);
 }
 
+template <typename real>
+hipError_t launch_receivers_t(int nshots, const RecArgs &a, hipStream_t st) {
+  switch (a.Np) {
+    case 4: hipLaunchKernelGGL((receiver_kernel<real, 4>), dim3(nshots), dim3(256), 0, st, a); break;
+    case 10: hipLaunchKernelGGL((receiver_kernel<real, 10>), dim3(nshots), dim3(256), 0, st, a); break;
+    case 20: hipLaunchKernelGGL((receiver_kernel<real, 20>), dim3(nshots), dim3(256), 0, st, a); break;
+    case 35: hipLaunchKernelGGL((receiver_kernel<real, 35>), dim3(nshots), dim3(256), 0, st, a); break;
+    case 56: hipLaunchKernelGGL((receiver_kernel<real, 56>), dim3(nshots), dim3(256), 0, st, a); break;
+    case 84: hipLaunchKernelGGL((receiver_kernel<real, 84>), dim3(nshots), dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_receivers(int precision, int nshots, const RecArgs &a,
                             hipStream_t st) {
-  if (precision == 64)
-    hipLaunchKernelGGL(receiver_kernel<double>, dim3(nshots), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(receiver_kernel<float>, dim3(nshots), dim3(256), 0, st, a);
-  return hipGetLastError();
+  if (precision == 64) return launch_receivers_t<double>(nshots, a, st);
+  return launch_receivers_t<float>(nshots, a, st);
 }
 
 hipError_t launch_energy(int precision, const void *q, int64_t K, int Np,
