@@ -644,22 +644,32 @@ inject_kernel(int Np, real *lam_q, int64_t shot_stride, const int32_t *nrec,
               const double *trace, int64_t cap, const double *d_obs,
               int64_t nobs, const int64_t *shot_step, const int64_t *shot_len,
               double dt) {
-  const int shot = blockIdx.x;
+  const int shot = blockIdx.y, r = blockIdx.x;
   const int64_t step = shot_step[shot];
   if (step >= shot_len[shot] || step >= cap || step >= nobs) return;
   const int nr = nrec[shot];
+  if (r >= nr) return;
+  // one work-group per receiver element: the work-group of the element's
+  // first receiver adds the contributions of all its receivers, in receiver
+  // order (the order of one sequential pass over the receivers), so no two
+  // work-groups touch the same entries and each entry is read and written
+  // once
+  const int32_t *re = rec_elem + (int64_t)shot * rmax;
+  const int64_t k = re[r];
+  for (int r0 = 0; r0 < r; ++r0)
+    if (re[r0] == k) return;   // uniform per work-group
   real *lq = lam_q + shot * shot_stride;
-  // thread (c, j) owns lam_q[k][c][j] of every receiver element: the
-  // receivers are visited in order, so shared elements never race
   for (int t = threadIdx.x; t < 3 * Np; t += blockDim.x) {
     const int c = t / Np, j = t - c * Np;
-    for (int r = 0; r < nr; ++r) {
-      const int64_t base = ((int64_t)shot * rmax + r) * 3 + c;
+    real v = lq[(k * 9 + c) * Np + j];
+    for (int r2 = r; r2 < nr; ++r2) {
+      if (re[r2] != k) continue;
+      const int64_t base = ((int64_t)shot * rmax + r2) * 3 + c;
       const double res = trace[base * cap + step] - d_obs[base * nobs + step];
-      const int64_t k = rec_elem[(int64_t)shot * rmax + r];
-      const double add = dt * rec_w[((int64_t)shot * rmax + r) * Np + j] * res;
-      lq[(k * 9 + c) * Np + j] += (real)add;
+      const double add = dt * rec_w[((int64_t)shot * rmax + r2) * Np + j] * res;
+      v += (real)add;
     }
+    lq[(k * 9 + c) * Np + j] = v;
   }
 }
 
@@ -710,11 +720,11 @@ hipError_t launch_inject(int precision, int nshots, int Np, void *lam_q,
                          int64_t nobs, const int64_t *shot_step,
                          const int64_t *shot_len, double dt, hipStream_t st) {
   if (precision == 64)
-    hipLaunchKernelGGL(inject_kernel<double>, dim3(nshots), dim3(256), 0, st, Np,
+    hipLaunchKernelGGL(inject_kernel<double>, dim3(rmax, nshots), dim3(256), 0, st, Np,
                        (double *)lam_q, shot_stride, nrec, rmax, rec_elem, rec_w,
                        trace, cap, d_obs, nobs, shot_step, shot_len, dt);
   else
-    hipLaunchKernelGGL(inject_kernel<float>, dim3(nshots), dim3(256), 0, st, Np,
+    hipLaunchKernelGGL(inject_kernel<float>, dim3(rmax, nshots), dim3(256), 0, st, Np,
                        (float *)lam_q, shot_stride, nrec, rmax, rec_elem, rec_w,
                        trace, cap, d_obs, nobs, shot_step, shot_len, dt);
   return hipGetLastError();
