@@ -378,9 +378,9 @@ def reverse_stage_bytes(K, Np, real_bytes):
 # while the reverse-sweep kernel source hashes to the value it was measured
 # for.
 MEASURED_ADJ_TRAFFIC = {
-    "kernel_source_sha256": "9a98fd44e4c1608177744cd8a54f66aa030605e22c3f4576f7748c02e17dd570",
-    "bytes_per_reverse_stage": {64: 365053747 + 132779930 // 5,
-                                32: 188596736 + 70089728 // 5},
+    "kernel_source_sha256": "19a17c02a27ece1b0ecd1c581d1e10221e7cbea7ceabb6bc75a89a02b7e32278",
+    "bytes_per_reverse_stage": {64: 365032528 + 132779902 // 5,
+                                32: 188583377 + 70089743 // 5},
 }
 
 
