@@ -178,6 +178,37 @@ def test_full_size_layered_fp32_bench_launch(kernel):
         assert err <= FP32_TOL and terr <= FP32_TOL
 
 
+@pytest.mark.parametrize("N", [5, 6])
+def test_order5_6_fp64_matrix_core_shapes(N):
+    """Orders 5 and 6 in FP64, where the matrix-core variant loads its
+    operator fragments through a register ring: every block size and a
+    persistent grid give bitwise the same fields, which match the oracle to
+    the FP64 bar."""
+    mesh = W.kuhn_cube(2, 1.0)
+    K = mesh["etov"].shape[0]
+    rho, lam, mu = _random_medium(K, 300 + N)
+    P = oracle_problem(mesh, N)
+    dt = P.suggest_dt(rho, lam, mu, 0.5)
+    q0 = random_fields(K, P.Np, 400 + N)
+    q_ora, _ = oracle_run(P, q0, rho, lam, mu, dt, 4)
+    blocks = {5: (6, 3), 6: (4, 2)}[N]
+    outs = []
+    for be in blocks:
+        for wpc in (0, 2):
+            say("case order %d fp64 matrix-core shape (1, %d, %d)" % (N, be, wpc))
+            s = gpu_solver(mesh, N, rho, lam, mu, dt)
+            s.set_launch(1, be, wpc)
+            s.set_fields(0, q0)
+            s.step(4)
+            outs.append(s.get_fields(0))
+            s.close()
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+    err = rel_l2(outs[0], q_ora)
+    say("order %d matrix-core fields vs oracle %.3e" % (N, err))
+    assert err <= FP64_TOL
+
+
 def test_full_size_order6_variants_agree_and_dissipate():
     """Order 6 (84 nodes) on the full 82944-element mesh, where the oracle
     is too slow for a full run: the two kernel variants agree to the FP64
