@@ -378,7 +378,7 @@ def reverse_stage_bytes(K, Np, real_bytes):
 # while the reverse-sweep kernel source hashes to the value it was measured
 # for.
 MEASURED_ADJ_TRAFFIC = {
-    "kernel_source_sha256": "19a17c02a27ece1b0ecd1c581d1e10221e7cbea7ceabb6bc75a89a02b7e32278",
+    "kernel_source_sha256": "1a2535ab18bda86aa257e174f0261d8e5d03a9fb37df74b379dff2408999f276",
     "bytes_per_reverse_stage": {64: 365032528 + 132779902 // 5,
                                 32: 188583377 + 70089743 // 5},
 }

@@ -481,9 +481,9 @@ __global__ void __launch_bounds__(kT) adj_main_kernel(AdjArgs<real> A) {
       const real *pr = A.Dr + i, *ps = A.Ds + i, *pt = A.Dt + i;
 #pragma unroll 1
       for (int j0 = 0; j0 < Np; j0 += UJ) {
-        // FP32: the chunk's operator entries are loaded together (the
-        // registers are there); FP64 keeps the compiler's one-step lead,
-        // whose registers keep three waves per SIMD
+        // the chunk's operator entries are loaded together: one round trip
+        // per chunk (with this node's lam_q loads after the loop, the
+        // registers still allow three waves per SIMD in FP64)
         real a0[UJ], a1[UJ], a2[UJ];
 #pragma unroll
         for (int u = 0; u < UJ; ++u) {
